@@ -1,0 +1,290 @@
+"""FP64 CPU oracle for the AMBER reionization-redshift hot path (test infrastructure).
+
+This package is the checker, not the product: only ``tests/``, the package smoke
+check and the benchmark's CPU-baseline leg import it.  It wraps the plain C
+definitions in ``amber_oracle.c`` (built with gcc, ``-ffp-contract=off``) and
+shares no code with the GPU library.
+
+Paper: Trac et al., "AMBER: A Semi-numerical Abundance Matching Box for the Epoch
+of Reionization", arXiv:2109.10375.  Each wrapper names the passage it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "amber_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK = 0
+E_ARG = -1
+E_HISTORY = -3
+E_DATA = -7
+E_RANGE = -8
+
+CONTRACT = 1
+EXACT = 0
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+            "-fPIC", "-shared", "-o", tmp, _SRC, "-lm",
+        ])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        d, i, i64, p = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+        pd = ctypes.POINTER(ctypes.c_double)
+        pi64 = ctypes.POINTER(ctypes.c_int64)
+        L.oracle_history_points.argtypes = [d, d, d, pd, pd]
+        L.oracle_weibull_x.argtypes = [d, d, d, d]
+        L.oracle_weibull_x.restype = d
+        L.oracle_weibull_z.argtypes = [d, d, d, d]
+        L.oracle_weibull_z.restype = d
+        L.oracle_weibull_fit.argtypes = [d, d, d, d, d, d, pd, pd, pd]
+        L.oracle_table_geometry.argtypes = [d, d, d, pd, pi64, pd]
+        L.oracle_table.argtypes = [d, d, d, d, i64, p]
+        L.oracle_kernel_hat.argtypes = [d, d]
+        L.oracle_kernel_hat.restype = d
+        L.oracle_dft3.argtypes = [i, p, p, i]
+        L.oracle_radiation.argtypes = [i, d, p, d, p, pd]
+        L.oracle_kernel_real.argtypes = [i, d, d, p]
+        L.oracle_direct_convolution.argtypes = [i, d, p, d, p]
+        L.oracle_dft_coeff_f32.argtypes = [i, p, i, i, i, pd, pd]
+        L.oracle_rank_f32.argtypes = [i64, p, p]
+        L.oracle_rank_f64.argtypes = [i64, p, p]
+        L.oracle_mass_fraction.argtypes = [i64, p, p, p]
+        L.oracle_zre_f32.argtypes = [i64, p, p, d, d, d, d, i64, d, p, i, p, p, p]
+        L.oracle_zre_f64.argtypes = [i64, p, p, d, d, d, d, i64, d, p, i, p, p, p]
+        L.oracle_zre_cells_f32.argtypes = [i64, p, p, i64, p, d, d, d, d, i64, d, p, i, p, p]
+        L.oracle_invert.argtypes = [i64, p, d, d, d, d, i64, d, p, i, p]
+        L.oracle_u128_to_double.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.oracle_u128_to_double.restype = d
+        L.oracle_num_threads.restype = i
+        _lib = L
+    return _lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: oracle error {code}")
+        self.code = code
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != OK:
+        raise OracleError(rc, what)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def num_threads() -> int:
+    return lib().oracle_num_threads()
+
+
+# ---------------------------------------------------------------- history ----
+
+def history_points(z_mid: float, delta_z: float, a_z: float) -> tuple[float, float]:
+    """Sec. 3.1.1, Eqs. (zear), (zlat), reading z_lat = z_ear - Delta_z."""
+    ze, zl = ctypes.c_double(), ctypes.c_double()
+    _check(lib().oracle_history_points(z_mid, delta_z, a_z, ctypes.byref(ze), ctypes.byref(zl)),
+           "history_points")
+    return ze.value, zl.value
+
+
+def weibull_x(z, a, b, c):
+    """Sec. 3.1.2, Eq. (weibull)."""
+    f = lib().oracle_weibull_x
+    return np.vectorize(lambda t: f(float(t), a, b, c))(z)
+
+
+def weibull_z(x, a, b, c):
+    """Sec. 3.1.2, inverse of Eq. (weibull)."""
+    f = lib().oracle_weibull_z
+    return np.vectorize(lambda t: f(float(t), a, b, c))(x)
+
+
+def weibull_fit(z_mid, delta_z, a_z, x_ear=0.0, x_mid=0.0, x_lat=0.0) -> tuple[float, float, float]:
+    """Appendix A: secant solve of f(c_w) = 0, then algebraic a_w, b_w."""
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().oracle_weibull_fit(z_mid, delta_z, a_z, x_ear, x_mid, x_lat,
+                                    ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "weibull_fit")
+    return a.value, b.value, c.value
+
+
+def table_geometry(a, b, c) -> tuple[float, int, float]:
+    """Contract-mode table geometry (h, T, z_top); see amber_oracle.c."""
+    h, T, zt = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    _check(lib().oracle_table_geometry(a, b, c, ctypes.byref(h), ctypes.byref(T), ctypes.byref(zt)),
+           "table_geometry")
+    return h.value, T.value, zt.value
+
+
+def table(a, b, c, h, T) -> np.ndarray:
+    X = np.empty(T + 1, dtype=np.float64)
+    _check(lib().oracle_table(a, b, c, h, T, _ptr(X)), "table")
+    return X
+
+
+class History:
+    """A fitted history: Weibull coefficients plus the contract table."""
+
+    def __init__(self, a, b, c):
+        self.a, self.b, self.c = float(a), float(b), float(c)
+        self.h, self.T, self.z_top = table_geometry(self.a, self.b, self.c)
+        self._X = None
+
+    @classmethod
+    def from_params(cls, z_mid, delta_z, a_z, x_ear=0.0, x_mid=0.0, x_lat=0.0):
+        return cls(*weibull_fit(z_mid, delta_z, a_z, x_ear, x_mid, x_lat))
+
+    @property
+    def X(self) -> np.ndarray:
+        if self._X is None:
+            self._X = table(self.a, self.b, self.c, self.h, self.T)
+        return self._X
+
+
+# -------------------------------------------------------------- radiation ----
+
+def kernel_hat(k: float, l_mfp: float) -> float:
+    """atan(k l)/k, the transform of exp(-r/l)/(4 pi r^2) (Sec. 3.4.1, Eq. intensity)."""
+    return lib().oracle_kernel_hat(float(k), float(l_mfp))
+
+
+def dft3(x: np.ndarray, sign: int = -1) -> np.ndarray:
+    """Naive separable 3D DFT (unnormalised)."""
+    n = x.shape[0]
+    re = np.ascontiguousarray(x.real, dtype=np.float64).copy()
+    im = np.ascontiguousarray(np.imag(x), dtype=np.float64).copy()
+    _check(lib().oracle_dft3(n, _ptr(re), _ptr(im), sign), "dft3")
+    return re + 1j * im
+
+
+def radiation(src: np.ndarray, box_len: float, l_mfp: float, return_imag: bool = False):
+    """J = IDFT[DFT(S) Khat] / N^3 in FP64 (Sec. 3.4.1)."""
+    n = src.shape[0]
+    s = np.ascontiguousarray(src, dtype=np.float64)
+    J = np.empty_like(s)
+    im = ctypes.c_double()
+    _check(lib().oracle_radiation(n, float(box_len), _ptr(s), float(l_mfp), _ptr(J), ctypes.byref(im)),
+           "radiation")
+    return (J, im.value) if return_imag else J
+
+
+def kernel_real(n: int, box_len: float, l_mfp: float) -> np.ndarray:
+    g = np.empty((n, n, n), dtype=np.float64)
+    _check(lib().oracle_kernel_real(n, float(box_len), float(l_mfp), _ptr(g)), "kernel_real")
+    return g
+
+
+def direct_convolution(src: np.ndarray, box_len: float, l_mfp: float) -> np.ndarray:
+    n = src.shape[0]
+    s = np.ascontiguousarray(src, dtype=np.float64)
+    J = np.empty_like(s)
+    _check(lib().oracle_direct_convolution(n, float(box_len), _ptr(s), float(l_mfp), _ptr(J)),
+           "direct_convolution")
+    return J
+
+
+def dft_coeff(field: np.ndarray, m: tuple[int, int, int]) -> complex:
+    """One DFT coefficient of an FP32 field, O(N^3)."""
+    f = np.ascontiguousarray(field, dtype=np.float32)
+    re, im = ctypes.c_double(), ctypes.c_double()
+    _check(lib().oracle_dft_coeff_f32(f.shape[0], _ptr(f), int(m[0]), int(m[1]), int(m[2]),
+                                      ctypes.byref(re), ctypes.byref(im)), "dft_coeff")
+    return complex(re.value, im.value)
+
+
+# ---------------------------------------------------------- abundance match --
+
+def rank(J: np.ndarray) -> np.ndarray:
+    """Descending rank order, ties by ascending cell index (Sec. 3.4.2, reading Z3)."""
+    flat = np.ascontiguousarray(J).reshape(-1)
+    perm = np.empty(flat.size, dtype=np.uint32)
+    if flat.dtype == np.float32:
+        rc = lib().oracle_rank_f32(flat.size, _ptr(flat), _ptr(perm))
+    else:
+        flat = flat.astype(np.float64, copy=False)
+        rc = lib().oracle_rank_f64(flat.size, _ptr(flat), _ptr(perm))
+    _check(rc, "rank")
+    return perm
+
+
+def mass_fraction(perm: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """Exact cumulative mass fraction in rank order (Sec. 3.4.2, reading Z4)."""
+    p = np.ascontiguousarray(perm, dtype=np.uint32).reshape(-1)
+    wf = np.ascontiguousarray(w, dtype=np.float32).reshape(-1)
+    F = np.empty(p.size, dtype=np.float64)
+    _check(lib().oracle_mass_fraction(p.size, _ptr(p), _ptr(wf), _ptr(F)), "mass_fraction")
+    return F
+
+
+def zre(J: np.ndarray, w: np.ndarray, hist: History, mode: int = CONTRACT,
+        want_perm: bool = False):
+    """Abundance match (Sec. 3.4.2): returns (z_re float32, z_re float64[, perm])."""
+    shape = J.shape
+    flat = np.ascontiguousarray(J).reshape(-1)
+    wf = np.ascontiguousarray(w, dtype=np.float32).reshape(-1)
+    n = flat.size
+    z32 = np.empty(n, dtype=np.float32)
+    z64 = np.empty(n, dtype=np.float64)
+    perm = np.empty(n, dtype=np.uint32)
+    X = hist.X if mode == CONTRACT else np.zeros(2)
+    args = (hist.a, hist.b, hist.c, hist.h, hist.T, hist.z_top, _ptr(X), mode, _ptr(z32), _ptr(z64), _ptr(perm))
+    if flat.dtype == np.float32:
+        rc = lib().oracle_zre_f32(n, _ptr(flat), _ptr(wf), *args)
+    else:
+        flat = flat.astype(np.float64, copy=False)
+        rc = lib().oracle_zre_f64(n, _ptr(flat), _ptr(wf), *args)
+    _check(rc, "zre")
+    out = (z32.reshape(shape), z64.reshape(shape))
+    return out + (perm,) if want_perm else out
+
+
+def zre_cells(J: np.ndarray, w: np.ndarray, cells, hist: History, mode: int = CONTRACT):
+    """z_re of selected cells, one by one in O(N) each; returns (z float32, F float64)."""
+    flat = np.ascontiguousarray(J, dtype=np.float32).reshape(-1)
+    wf = np.ascontiguousarray(w, dtype=np.float32).reshape(-1)
+    c = np.ascontiguousarray(np.asarray(cells, dtype=np.int64))
+    z = np.empty(c.size, dtype=np.float32)
+    F = np.empty(c.size, dtype=np.float64)
+    X = hist.X if mode == CONTRACT else np.zeros(2)
+    _check(lib().oracle_zre_cells_f32(flat.size, _ptr(flat), _ptr(wf), c.size, _ptr(c),
+                                      hist.a, hist.b, hist.c, hist.h, hist.T, hist.z_top,
+                                      _ptr(X), mode, _ptr(z), _ptr(F)), "zre_cells")
+    return z, F
+
+
+def invert(F, hist: History, mode: int = CONTRACT) -> np.ndarray:
+    """z = x_i^{-1}(F): closed form (exact mode) or table interpolation (contract)."""
+    f = np.ascontiguousarray(F, dtype=np.float64).reshape(-1)
+    z = np.empty_like(f)
+    X = hist.X if mode == CONTRACT else np.zeros(2)
+    _check(lib().oracle_invert(f.size, _ptr(f), hist.a, hist.b, hist.c, hist.h, hist.T, hist.z_top,
+                               _ptr(X), mode, _ptr(z)), "invert")
+    return z
+
+
+def u128_to_double(v: int) -> float:
+    return lib().oracle_u128_to_double((v >> 64) & ((1 << 64) - 1), v & ((1 << 64) - 1))

@@ -1,0 +1,580 @@
+/*
+ * amber_oracle.c -- plain, slow, FP64 CPU oracle for the reionization-redshift
+ * hot path of AMBER (Trac, Chen, Holst, Alvarez & Cen, "AMBER: A
+ * Semi-numerical Abundance Matching Box for the Epoch of Reionization",
+ * arXiv:2109.10375).
+ *
+ * TEST INFRASTRUCTURE.  This file exists to check the GPU library.  Only the
+ * test suite, the package smoke check and the benchmark's CPU-baseline leg may
+ * load it.  It shares no code, header, table or constant generator with the
+ * GPU library, and it never reads anything the GPU library produced.
+ *
+ * Every routine is the plain definition of what the method computes, written
+ * out in FP64 (FP32 inputs are exact in FP64):
+ *   - reionization history points   : Sec. 3.1.1, Eqs. (zear), (zlat)
+ *   - Weibull history and inverse   : Sec. 3.1.2, Eq. (weibull) and its inverse
+ *   - Weibull coefficient solve     : Appendix A (secant on f(c_w), then the
+ *                                     algebraic a_w, b_w)
+ *   - radiation field               : Sec. 3.4.1, Eq. (intensity), evaluated as
+ *                                     a periodic convolution through discrete
+ *                                     Fourier transforms, with the kernel's
+ *                                     closed-form transform atan(k l)/k
+ *   - abundance matching            : Sec. 3.4.2, the cumulative-mass equation
+ *                                     (unnumbered) with weights 1+delta
+ *
+ * Readings of points the paper leaves open (each is listed in the design notes):
+ *   R1 the spectral kernel is atan(k l_mfp)/k sampled at the discrete
+ *      wavenumbers k_m = (2 pi / L)|m~|, m~ the signed integer frequency, with
+ *      value l_mfp at k = 0;
+ *   R2 the inverse transform carries the 1/N^3 normalisation;
+ *   Z1 z_lat = z_ear - Delta_z (the middle expression printed for z_lat in
+ *      Sec. 3.1.1 contradicts its own right-hand side and Table 1);
+ *   Z2 a history is accepted when a_w, b_w, c_w > 0 and 0 < A_z <= 15;
+ *   Z3 rank order: intensity descending, ties by ascending row-major cell
+ *      index, -0 equal to +0, NaN rejected;
+ *   Z4 the cumulative mass is the exact sum (fixed point), F_n = RN(C_n)/RN(C_N);
+ *   Z5 F = 1 maps to z = a_w;
+ *   Z6 contract inversion by monotone table interpolation (geometry below);
+ *   Z7 weights are 1+delta at z_mid (growth factor ratio 1).
+ *
+ * Parity pins for each routine live in tests/test_oracle_*.py.
+ */
+#define _GNU_SOURCE
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_OK 0
+#define OR_E_ARG (-1)
+#define OR_E_HISTORY (-3)
+#define OR_E_DATA (-7)
+#define OR_E_RANGE (-8)
+
+typedef unsigned __int128 u128;
+
+/* ------------------------------------------------------------------------ */
+/* Reionization history: Sec. 3.1.1 and Sec. 3.1.2                          */
+/* ------------------------------------------------------------------------ */
+
+/* Eqs. (duration), (asymmetry) solved for the early and late redshifts:
+ * z_ear = z_mid + Delta_z A_z / (1 + A_z), z_lat = z_ear - Delta_z  (reading Z1). */
+int oracle_history_points(double z_mid, double delta_z, double a_z,
+                          double* z_ear, double* z_lat) {
+    if (!(delta_z > 0.0) || !(a_z > 0.0) || !isfinite(z_mid)) return OR_E_ARG;
+    *z_ear = z_mid + delta_z * a_z / (1.0 + a_z);
+    *z_lat = *z_ear - delta_z;
+    return OR_OK;
+}
+
+/* Eq. (weibull): x_i(z) = exp[-max((z - a_w)/b_w, 0)^c_w]. */
+double oracle_weibull_x(double z, double a, double b, double c) {
+    double u = (z - a) / b;
+    if (u < 0.0) u = 0.0;
+    return exp(-pow(u, c));
+}
+
+/* Inverse of Eq. (weibull): z = a_w + b_w |ln x|^(1/c_w). */
+double oracle_weibull_z(double x, double a, double b, double c) {
+    return a + b * pow(fabs(log(x)), 1.0 / c);
+}
+
+/* Appendix A: f(c_w) = (ln x_ear / ln x_mid)^(1/c_w) - (z_ear - a)/(z_mid - a),
+ * a = (z_lat |ln x_mid|^(1/c) - z_mid |ln x_lat|^(1/c)) /
+ *     (|ln x_mid|^(1/c) - |ln x_lat|^(1/c)). */
+static double weibull_f(double c, double z_ear, double z_mid, double z_lat,
+                        double x_ear, double x_mid, double x_lat) {
+    double pm = pow(fabs(log(x_mid)), 1.0 / c);
+    double pl = pow(fabs(log(x_lat)), 1.0 / c);
+    double a = (z_lat * pm - z_mid * pl) / (pm - pl);
+    return pow(log(x_ear) / log(x_mid), 1.0 / c) - (z_ear - a) / (z_mid - a);
+}
+
+/* Appendix A: root of f(c_w) by the secant method (Newton with a finite
+ * difference), kept inside a sign-change bracket so that it always converges;
+ * then the algebraic a_w and b_w.  Ionization points default to
+ * (0.05, 0.5, 0.95) (Sec. 3.1.1) when passed as 0. */
+int oracle_weibull_fit(double z_mid, double delta_z, double a_z,
+                       double x_ear, double x_mid, double x_lat,
+                       double* a_w, double* b_w, double* c_w) {
+    double z_ear, z_lat;
+    if (x_ear == 0.0) x_ear = 0.05;
+    if (x_mid == 0.0) x_mid = 0.5;
+    if (x_lat == 0.0) x_lat = 0.95;
+    if (!(0.0 < x_ear && x_ear < x_mid && x_mid < x_lat && x_lat < 1.0)) return OR_E_ARG;
+    if (oracle_history_points(z_mid, delta_z, a_z, &z_ear, &z_lat) != OR_OK) return OR_E_ARG;
+    if (a_z > 15.0) return OR_E_HISTORY;
+
+    /* f > 0 for small c_w and f < 0 for large c_w whenever a root exists; scan
+     * powers of two for a sign change. */
+    double lo = 0.0, hi = 0.0, flo = 0.0, fhi = 0.0;
+    int found = 0;
+    double cprev = ldexp(1.0, -6);
+    double fprev = weibull_f(cprev, z_ear, z_mid, z_lat, x_ear, x_mid, x_lat);
+    for (int k = -5; k <= 12; ++k) {
+        double cc = ldexp(1.0, k);
+        double fc = weibull_f(cc, z_ear, z_mid, z_lat, x_ear, x_mid, x_lat);
+        if (isfinite(fprev) && isfinite(fc) && fprev > 0.0 && fc <= 0.0) {
+            lo = cprev; hi = cc; flo = fprev; fhi = fc; found = 1;
+            break;
+        }
+        cprev = cc; fprev = fc;
+    }
+    if (!found) return OR_E_HISTORY;
+    if (fhi == 0.0) {
+        lo = hi; flo = fhi;
+    }
+    /* Secant iterates (c0, c1); fall back to bisection when the secant step
+     * leaves the bracket. */
+    double c0 = lo, f0 = flo, c1 = hi, f1 = fhi, c = hi;
+    for (int it = 0; it < 400 && lo != hi; ++it) {
+        double cn;
+        if (f1 != f0) cn = c1 - f1 * (c1 - c0) / (f1 - f0);
+        else cn = 0.5 * (lo + hi);
+        if (!(cn > lo && cn < hi)) cn = 0.5 * (lo + hi);
+        double fn = weibull_f(cn, z_ear, z_mid, z_lat, x_ear, x_mid, x_lat);
+        c = cn;
+        if (fn == 0.0) break;
+        if (fn > 0.0) { lo = cn; flo = fn; } else { hi = cn; fhi = fn; }
+        if (fabs(cn - c1) <= 1e-15 * fabs(cn)) break;
+        c0 = c1; f0 = f1; c1 = cn; f1 = fn;
+    }
+    double pe = pow(fabs(log(x_ear)), 1.0 / c);
+    double pm = pow(fabs(log(x_mid)), 1.0 / c);
+    double pl = pow(fabs(log(x_lat)), 1.0 / c);
+    double a = (z_ear * pl - z_lat * pe) / (pl - pe);
+    double b = (z_mid - a) / pm;
+    if (!(a > 0.0) || !(b > 0.0) || !(c > 0.0) || !isfinite(a) || !isfinite(b))
+        return OR_E_HISTORY;
+    *a_w = a; *b_w = b; *c_w = c;
+    return OR_OK;
+}
+
+/* Contract-mode inversion table geometry (reading Z6):
+ *   z_top = a + b * (64 ln 2)^(1/c)      (x_i(z_top) = 2^-64)
+ *   h     = the smallest power of two >= (z_top - a) / 2^22
+ *   T     = ceil((z_top - a) / h)         (T <= 2^22)
+ *   nodes z_j = a + j h, X_j = x_i(z_j), j = 0..T. */
+int oracle_table_geometry(double a, double b, double c,
+                          double* h, int64_t* T, double* z_top) {
+    if (!(a > 0.0) || !(b > 0.0) || !(c > 0.0)) return OR_E_HISTORY;
+    double top = a + b * pow(64.0 * 0.69314718055994530942, 1.0 / c);
+    double span = top - a;
+    double r = span / 4194304.0;
+    int e;
+    double f = frexp(r, &e);           /* r = f 2^e, f in [0.5, 1) */
+    double hh = (f == 0.5) ? r : ldexp(1.0, e);
+    *h = hh;
+    *T = (int64_t)ceil(span / hh);
+    *z_top = top;
+    return OR_OK;
+}
+
+int oracle_table(double a, double b, double c, double h, int64_t T, double* X) {
+    for (int64_t j = 0; j <= T; ++j) {
+        double z = a + (double)j * h;
+        X[j] = exp(-pow((z - a) / b, c));
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Radiation field: Sec. 3.4.1                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Signed frequency of index m on an n-point periodic axis. */
+static int signed_freq(int m, int n) { return (2 * m <= n) ? m : m - n; }
+
+/* Fourier transform of exp(-r/l)/(4 pi r^2): (1/k) int_0^inf e^(-r/l) sin(kr)/r dr
+ * = atan(k l)/k, and l at k = 0. */
+double oracle_kernel_hat(double k, double l_mfp) {
+    if (k == 0.0) return l_mfp;
+    return atan(k * l_mfp) / k;
+}
+
+static void twiddles(int n, double* cs, double* sn) {
+    for (int j = 0; j < n; ++j) {
+        double t = 2.0 * M_PI * (double)j / (double)n;
+        cs[j] = cos(t);
+        sn[j] = sin(t);
+    }
+}
+
+/* One axis of the 3D DFT of a complex n^3 array (row-major, z fastest):
+ * out[.., k, ..] = sum_j in[.., j, ..] exp(sign * 2 pi i j k / n), with the
+ * angle reduced by the exact integer (j k) mod n. */
+static void dft_axis(int n, double* re, double* im, int axis, int sign,
+                     const double* cs, const double* sn) {
+    const int64_t n2 = (int64_t)n * n;
+    const int64_t stride = (axis == 0) ? n2 : (axis == 1) ? n : 1;
+#pragma omp parallel
+    {
+        double* lr = (double*)malloc(sizeof(double) * (size_t)n);
+        double* li = (double*)malloc(sizeof(double) * (size_t)n);
+#pragma omp for schedule(static)
+        for (int64_t line = 0; line < n2; ++line) {
+            int64_t p = line / n, q = line % n, base;
+            if (axis == 0) base = p * n + q;
+            else if (axis == 1) base = p * n2 + q;
+            else base = p * n2 + q * n;
+            for (int j = 0; j < n; ++j) {
+                lr[j] = re[base + j * stride];
+                li[j] = im[base + j * stride];
+            }
+            for (int k = 0; k < n; ++k) {
+                double sr = 0.0, si = 0.0;
+                for (int j = 0; j < n; ++j) {
+                    int t = (int)(((int64_t)j * k) % n);
+                    double c = cs[t], s = sign * sn[t];
+                    sr += lr[j] * c - li[j] * s;
+                    si += lr[j] * s + li[j] * c;
+                }
+                re[base + k * stride] = sr;
+                im[base + k * stride] = si;
+            }
+        }
+        free(lr);
+        free(li);
+    }
+}
+
+/* Full 3D DFT (sign -1 forward, +1 inverse, unnormalised), in place. */
+int oracle_dft3(int n, double* re, double* im, int sign) {
+    if (n < 1 || (sign != 1 && sign != -1)) return OR_E_ARG;
+    double* cs = (double*)malloc(sizeof(double) * (size_t)n);
+    double* sn = (double*)malloc(sizeof(double) * (size_t)n);
+    twiddles(n, cs, sn);
+    for (int axis = 0; axis < 3; ++axis) dft_axis(n, re, im, axis, sign, cs, sn);
+    free(cs);
+    free(sn);
+    return OR_OK;
+}
+
+/* J = IDFT[ DFT(S) * Khat(|k|; l_mfp) ] / n^3 (real part), Sec. 3.4.1 with
+ * readings R1, R2.  imag_max receives max |Im J| (a self-check). */
+int oracle_radiation(int n, double box_len, const double* src, double l_mfp,
+                     double* J, double* imag_max) {
+    if (n < 1 || !(box_len > 0.0) || !(l_mfp > 0.0)) return OR_E_ARG;
+    const int64_t n3 = (int64_t)n * n * n;
+    double* re = (double*)malloc(sizeof(double) * (size_t)n3);
+    double* im = (double*)calloc((size_t)n3, sizeof(double));
+    if (!re || !im) { free(re); free(im); return OR_E_ARG; }
+    memcpy(re, src, sizeof(double) * (size_t)n3);
+    oracle_dft3(n, re, im, -1);
+    const double k0 = 2.0 * M_PI / box_len;
+    for (int mx = 0; mx < n; ++mx)
+        for (int my = 0; my < n; ++my)
+            for (int mz = 0; mz < n; ++mz) {
+                int sx = signed_freq(mx, n), sy = signed_freq(my, n), sz = signed_freq(mz, n);
+                double k = k0 * sqrt((double)sx * sx + (double)sy * sy + (double)sz * sz);
+                double g = oracle_kernel_hat(k, l_mfp);
+                int64_t i = ((int64_t)mx * n + my) * n + mz;
+                re[i] *= g;
+                im[i] *= g;
+            }
+    oracle_dft3(n, re, im, +1);
+    double mi = 0.0;
+    for (int64_t i = 0; i < n3; ++i) {
+        J[i] = re[i] / (double)n3;
+        double a = fabs(im[i] / (double)n3);
+        if (a > mi) mi = a;
+    }
+    if (imag_max) *imag_max = mi;
+    free(re);
+    free(im);
+    return OR_OK;
+}
+
+/* Real-space periodic kernel g(n) = (1/n^3) sum_m Khat(k_m) e^{+2 pi i m.n/n},
+ * by the direct (non-separable) triple sum; O(n^6), tiny n only. */
+int oracle_kernel_real(int n, double box_len, double l_mfp, double* g) {
+    if (n < 1 || n > 24) return OR_E_ARG;
+    const double k0 = 2.0 * M_PI / box_len;
+    const int64_t n3 = (int64_t)n * n * n;
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < n3; ++p) {
+        int px = (int)(p / ((int64_t)n * n)), py = (int)((p / n) % n), pz = (int)(p % n);
+        double s = 0.0;
+        for (int mx = 0; mx < n; ++mx)
+            for (int my = 0; my < n; ++my)
+                for (int mz = 0; mz < n; ++mz) {
+                    int sx = signed_freq(mx, n), sy = signed_freq(my, n), sz = signed_freq(mz, n);
+                    double k = k0 * sqrt((double)sx * sx + (double)sy * sy + (double)sz * sz);
+                    double ph = 2.0 * M_PI * (double)(((int64_t)mx * px + (int64_t)my * py + (int64_t)mz * pz) % n) / n;
+                    s += oracle_kernel_hat(k, l_mfp) * cos(ph);
+                }
+        g[p] = s / (double)n3;
+    }
+    return OR_OK;
+}
+
+/* Brute-force periodic convolution J(n) = sum_{n'} S(n') g(n - n'); O(n^6). */
+int oracle_direct_convolution(int n, double box_len, const double* src, double l_mfp, double* J) {
+    if (n < 1 || n > 24) return OR_E_ARG;
+    const int64_t n3 = (int64_t)n * n * n;
+    double* g = (double*)malloc(sizeof(double) * (size_t)n3);
+    oracle_kernel_real(n, box_len, l_mfp, g);
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < n3; ++p) {
+        int px = (int)(p / ((int64_t)n * n)), py = (int)((p / n) % n), pz = (int)(p % n);
+        double s = 0.0;
+        for (int64_t q = 0; q < n3; ++q) {
+            int qx = (int)(q / ((int64_t)n * n)), qy = (int)((q / n) % n), qz = (int)(q % n);
+            int dx = (px - qx + n) % n, dy = (py - qy + n) % n, dz = (pz - qz + n) % n;
+            s += src[q] * g[((int64_t)dx * n + dy) * n + dz];
+        }
+        J[p] = s;
+    }
+    free(g);
+    return OR_OK;
+}
+
+/* One DFT coefficient of a real FP32 field: sum_n f_n e^{-2 pi i m.n/N}.
+ * O(N^3); used to check full-size GPU output at sampled wavevectors. */
+int oracle_dft_coeff_f32(int n, const float* f, int mx, int my, int mz,
+                         double* out_re, double* out_im) {
+    double* cs = (double*)malloc(sizeof(double) * (size_t)n);
+    double* sn = (double*)malloc(sizeof(double) * (size_t)n);
+    twiddles(n, cs, sn);
+    double sr = 0.0, si = 0.0;
+#pragma omp parallel for reduction(+ : sr, si) schedule(static)
+    for (int x = 0; x < n; ++x)
+        for (int y = 0; y < n; ++y) {
+            const float* row = f + ((int64_t)x * n + y) * n;
+            int64_t base = (int64_t)mx * x + (int64_t)my * y;
+            for (int z = 0; z < n; ++z) {
+                int t = (int)((base + (int64_t)mz * z) % n);
+                sr += (double)row[z] * cs[t];
+                si -= (double)row[z] * sn[t];
+            }
+        }
+    *out_re = sr;
+    *out_im = si;
+    free(cs);
+    free(sn);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Abundance matching: Sec. 3.4.2                                           */
+/* ------------------------------------------------------------------------ */
+
+struct rank_ctx { const float* v32; const double* v64; };
+
+/* Descending value, ties by ascending cell index (reading Z3). */
+static int rank_cmp(const void* pa, const void* pb, void* pctx) {
+    const struct rank_ctx* ctx = (const struct rank_ctx*)pctx;
+    uint32_t i = *(const uint32_t*)pa, j = *(const uint32_t*)pb;
+    double x = ctx->v32 ? (double)ctx->v32[i] : ctx->v64[i];
+    double y = ctx->v32 ? (double)ctx->v32[j] : ctx->v64[j];
+    if (x > y) return -1;
+    if (x < y) return 1;
+    return (i < j) ? -1 : (i > j) ? 1 : 0;
+}
+
+static int rank_any(int64_t n, const float* v32, const double* v64, uint32_t* perm) {
+    if (n < 0 || n > ((int64_t)1 << 32)) return OR_E_ARG;
+    for (int64_t i = 0; i < n; ++i) {
+        double v = v32 ? (double)v32[i] : v64[i];
+        if (isnan(v)) return OR_E_DATA;
+        perm[i] = (uint32_t)i;
+    }
+    struct rank_ctx ctx = {v32, v64};
+    qsort_r(perm, (size_t)n, sizeof(uint32_t), rank_cmp, &ctx);
+    return OR_OK;
+}
+
+/* "the data array is ranked in descending order" (Sec. 3.4.2). */
+int oracle_rank_f32(int64_t n, const float* J, uint32_t* perm) { return rank_any(n, J, NULL, perm); }
+int oracle_rank_f64(int64_t n, const double* J, uint32_t* perm) { return rank_any(n, NULL, J, perm); }
+
+/* Exact fixed-point decomposition of a positive finite FP32 weight:
+ * w = m 2^q with q the exponent of w's unit in the last place as an FP32
+ * number (q = e - 24 from w = f 2^e, f in [0.5, 1), but at least -149 for
+ * subnormals), so m < 2^24 is an integer. */
+static int weight_parts(float wf, uint64_t* m, int* q) {
+    double w = (double)wf;
+    if (!isfinite(w) || !(w > 0.0)) return OR_E_DATA;
+    int e;
+    frexp(w, &e);
+    int qq = e - 24;
+    if (qq < -149) qq = -149;
+    *m = (uint64_t)ldexp(w, -qq);
+    *q = qq;
+    return OR_OK;
+}
+
+static int bit_length64(uint64_t v) {
+    int b = 0;
+    while (v) { ++b; v >>= 1; }
+    return b;
+}
+
+struct mass_scale { int qmin; u128 total; };
+
+static int mass_scale_of(int64_t n, const float* w, struct mass_scale* ms) {
+    int qmin = 1 << 30;
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t m; int q;
+        if (weight_parts(w[i], &m, &q) != OR_OK) return OR_E_DATA;
+        if (q < qmin) qmin = q;
+    }
+    /* The exact total of w 2^-qmin must stay below 2^127 (else a range error). */
+    u128 tot = 0;
+    const u128 lim = (u128)1 << 127;
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t m; int q;
+        weight_parts(w[i], &m, &q);
+        int sh = q - qmin;
+        if (sh + bit_length64(m) > 127) return OR_E_RANGE;
+        u128 t = (u128)m << sh;
+        if (t >= lim - tot) return OR_E_RANGE;
+        tot += t;
+    }
+    ms->qmin = qmin;
+    ms->total = tot;
+    return OR_OK;
+}
+
+static u128 scaled_weight(float wf, int qmin) {
+    uint64_t m; int q;
+    weight_parts(wf, &m, &q);
+    return (u128)m << (q - qmin);
+}
+
+/* Cumulative ionized-mass fraction in rank order, Sec. 3.4.2:
+ * F_n = RN(sum_{k<=n} w_perm[k]) / RN(sum_k w_k), sums exact (reading Z4). */
+int oracle_mass_fraction(int64_t n, const uint32_t* perm, const float* w, double* F) {
+    struct mass_scale ms;
+    int rc = mass_scale_of(n, w, &ms);
+    if (rc != OR_OK) return rc;
+    const double tot = (double)ms.total;
+    u128 c = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        c += scaled_weight(w[perm[k]], ms.qmin);
+        F[k] = (double)c / tot;
+    }
+    return OR_OK;
+}
+
+/* z = x_i^{-1}(F) by the closed form (exact mode) or by table interpolation
+ * (contract mode), clamped to z_top (readings Z5, Z6). */
+static double invert_exact(double F, double a, double b, double c, double z_top) {
+    double z = a + b * pow(-log(F), 1.0 / c);
+    return (z < z_top) ? z : z_top;
+}
+
+static double invert_table(double F, double a, double h, int64_t T, double z_top, const double* X) {
+    /* j = max{ j in [0, T] : X_j >= F }; X_0 = 1 >= F. */
+    int64_t lo = 0, hi = T;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo + 1) / 2;
+        if (X[mid] >= F) lo = mid; else hi = mid - 1;
+    }
+    int64_t j = (lo > T - 1) ? T - 1 : lo;
+    double zj = a + (double)j * h;
+    double zj1 = a + (double)(j + 1) * h;
+    double den = X[j] - X[j + 1];
+    double t = (den != 0.0) ? (X[j] - F) / den : 0.0;
+    double dz = zj1 - zj;
+    double z = zj + t * dz;
+    return (z < z_top) ? z : z_top;
+}
+
+/* Inversion of an array of mass fractions (used by the inversion pins). */
+int oracle_invert(int64_t n, const double* F, double a, double b, double c, double h,
+                  int64_t T, double z_top, const double* X, int mode, double* z) {
+    for (int64_t k = 0; k < n; ++k) {
+        if (!(F[k] > 0.0 && F[k] <= 1.0)) return OR_E_ARG;
+        z[k] = (mode == 0) ? invert_exact(F[k], a, b, c, z_top)
+                           : invert_table(F[k], a, h, T, z_top, X);
+    }
+    return OR_OK;
+}
+
+/* Full abundance match: rank (FP32 or FP64 intensity), exact cumulative mass,
+ * inversion, z_re[perm[n]] = z_n.  mode 0 = exact, 1 = contract (table X of
+ * T+1 entries with the geometry of oracle_table_geometry). */
+static int zre_any(int64_t n, const float* J32, const double* J64, const float* w,
+                   double a, double b, double c, double h, int64_t T, double z_top,
+                   const double* X, int mode, float* zre, double* zre64, uint32_t* perm_out) {
+    uint32_t* perm = perm_out ? perm_out : (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    double* F = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int rc = rank_any(n, J32, J64, perm);
+    if (rc == OR_OK) rc = oracle_mass_fraction(n, perm, w, F);
+    if (rc == OR_OK) {
+        for (int64_t k = 0; k < n; ++k) {
+            double z = (mode == 0) ? invert_exact(F[k], a, b, c, z_top)
+                                   : invert_table(F[k], a, h, T, z_top, X);
+            if (zre) zre[perm[k]] = (float)z;
+            if (zre64) zre64[perm[k]] = z;
+        }
+    }
+    free(F);
+    if (!perm_out) free(perm);
+    return rc;
+}
+
+int oracle_zre_f32(int64_t n, const float* J, const float* w, double a, double b, double c,
+                   double h, int64_t T, double z_top, const double* X, int mode,
+                   float* zre, double* zre64, uint32_t* perm) {
+    return zre_any(n, J, NULL, w, a, b, c, h, T, z_top, X, mode, zre, zre64, perm);
+}
+
+int oracle_zre_f64(int64_t n, const double* J, const float* w, double a, double b, double c,
+                   double h, int64_t T, double z_top, const double* X, int mode,
+                   float* zre, double* zre64, uint32_t* perm) {
+    return zre_any(n, NULL, J, w, a, b, c, h, T, z_top, X, mode, zre, zre64, perm);
+}
+
+/* z_re of selected cells one by one, O(n) each: C(i) = sum of w_j over the
+ * cells ranked at or before i (descending J, ties by index). */
+int oracle_zre_cells_f32(int64_t n, const float* J, const float* w, int64_t n_cells,
+                         const int64_t* cells, double a, double b, double c,
+                         double h, int64_t T, double z_top, const double* X, int mode,
+                         float* zre_out, double* F_out) {
+    struct mass_scale ms;
+    for (int64_t i = 0; i < n; ++i)
+        if (isnan(J[i])) return OR_E_DATA;
+    int rc = mass_scale_of(n, w, &ms);
+    if (rc != OR_OK) return rc;
+    const double tot = (double)ms.total;
+    for (int64_t s = 0; s < n_cells; ++s) {
+        int64_t i = cells[s];
+        if (i < 0 || i >= n) return OR_E_ARG;
+        const float ji = J[i];
+        u128 cum = 0;
+#pragma omp parallel
+        {
+            u128 part = 0;
+#pragma omp for schedule(static)
+            for (int64_t j = 0; j < n; ++j) {
+                if (J[j] > ji || (J[j] == ji && j <= i)) part += scaled_weight(w[j], ms.qmin);
+            }
+#pragma omp critical
+            cum += part;
+        }
+        double F = (double)cum / tot;
+        double z = (mode == 0) ? invert_exact(F, a, b, c, z_top) : invert_table(F, a, h, T, z_top, X);
+        zre_out[s] = (float)z;
+        if (F_out) F_out[s] = F;
+    }
+    return OR_OK;
+}
+
+/* Exact u128 -> double helper exposed for the rounding pins. */
+double oracle_u128_to_double(uint64_t hi, uint64_t lo) {
+    u128 v = ((u128)hi << 64) | lo;
+    return (double)v;
+}
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
