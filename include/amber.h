@@ -1,0 +1,160 @@
+/*
+ * amber.h -- C-ABI of the MI355X (gfx950) library for the reionization-redshift
+ * hot path of AMBER (Trac et al., "AMBER: A Semi-numerical Abundance Matching
+ * Box for the Epoch of Reionization", arXiv:2109.10375).
+ *
+ * Two device stages, each a single asynchronous call on a HIP stream:
+ *   amber_radiation : J = S * [exp(-r/l_mfp) / (4 pi r^2)] on a periodic N^3
+ *                     grid (Sec. 3.4.1, Eq. intensity), by forward real 3D FFT,
+ *                     multiplication by the kernel transform atan(k l_mfp)/k and
+ *                     inverse FFT;
+ *   amber_zre       : abundance matching (Sec. 3.4.2): cells ranked by J
+ *                     (higher first), gas mass 1+delta summed in that order,
+ *                     z_re assigned so that the ionized mass fraction equals the
+ *                     Weibull history x_i(z) (Sec. 3.1.2, Eq. weibull).
+ * plus host-side helpers for the history (Sec. 3.1, Appendix A).
+ *
+ * Conventions for every call:
+ *   - fields are N^3 FP32 arrays in row-major order, z fastest: cell (x, y, z)
+ *     is element (x * N + y) * N + z.  "d_" pointers are device pointers on the
+ *     device that was current when the plan was created; "host" pointers are
+ *     ordinary host memory.
+ *   - the caller owns every buffer and stream; the library owns plans.  Compute
+ *     calls never allocate: all scratch comes from a caller-provided device
+ *     workspace of at least amber_workspace_bytes() bytes, which may be reused
+ *     once the stream has passed the call.  Calls sharing one workspace must be
+ *     ordered on one stream.
+ *   - compute calls return after enqueueing work on `stream` (a hipStream_t; NULL
+ *     is the default stream).  Results are deterministic and do not depend on
+ *     the launch order of other work.
+ *   - errors are returned as negative codes and never abort.  Argument errors
+ *     are found on the host before anything is enqueued.  Data errors found on
+ *     the device (NaN intensity, non-positive or non-finite weights, a mass sum
+ *     wider than 127 bits) set bits of a status word in the workspace, read by
+ *     amber_status(); the outputs of such a call are unspecified.
+ */
+#ifndef AMBER_H
+#define AMBER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define AMBER_OK 0
+#define AMBER_E_ARG (-1)        /* null pointer, bad count, non-finite parameter   */
+#define AMBER_E_SIZE (-2)       /* grid size not supported                          */
+#define AMBER_E_HISTORY (-3)    /* no positive Weibull coefficients for a history   */
+#define AMBER_E_WORKSPACE (-4)  /* workspace too small                              */
+#define AMBER_E_HIP (-5)        /* a HIP runtime call failed                        */
+#define AMBER_E_UNIMPL (-6)     /* not implemented                                  */
+
+/* Device status bits reported by amber_status(). */
+#define AMBER_STATUS_NAN_J 1u   /* an intensity was NaN (no rank order exists)      */
+#define AMBER_STATUS_BAD_W 2u   /* a weight was <= 0, NaN or infinite               */
+#define AMBER_STATUS_RANGE 4u   /* exact mass sum needs more than 127 bits          */
+
+typedef struct amber_plan_s* amber_plan;
+
+/* Reionization-history parameters, Sec. 3.1.1: midpoint, duration, asymmetry and
+ * the ionization fractions at the early, middle and late redshifts.  An x_* of 0
+ * selects the paper's default (0.05, 0.5, 0.95). */
+typedef struct {
+    double z_mid, delta_z, a_z;
+    double x_ear, x_mid, x_lat;
+} amber_history;
+
+/* A fitted history: Weibull coefficients (Sec. 3.1.2) and the geometry of the
+ * inversion table used by amber_zre.
+ *   z_top   = a_w + b_w (64 ln 2)^(1/c_w)        (x_i(z_top) = 2^-64)
+ *   h       = smallest power of two >= (z_top - a_w) / 2^22
+ *   table_n = T + 1 with T = ceil((z_top - a_w) / h); node j is z_j = a_w + j h
+ *             and holds X_j = exp(-((z_j - a_w)/b_w)^c_w) (FP64)
+ * d_table must point to T + 1 doubles on the device holding exactly the values
+ * written by amber_weibull_table() for this struct. */
+typedef struct {
+    double a_w, b_w, c_w;
+    double h, z_top;
+    int64_t table_n;
+    const double* d_table;
+} amber_weibull;
+
+/* ---- host-side helpers (no device work) -------------------------------- */
+
+const char* amber_version(void);
+const char* amber_strerror(int code);
+
+/* Appendix A: z_ear = z_mid + Delta_z A_z/(1 + A_z), z_lat = z_ear - Delta_z
+ * (Sec. 3.1.1), then the root c_w of the Appendix-A equation and the algebraic
+ * a_w, b_w.  Fills everything except d_table.  AMBER_E_HISTORY when a
+ * coefficient would not be positive or A_z > 15 (Sec. 3.1.2's stated range);
+ * AMBER_E_ARG for Delta_z <= 0, A_z <= 0 or unordered ionization points. */
+int amber_weibull_fit(const amber_history* hist, amber_weibull* out);
+
+/* Table geometry for given coefficients (all > 0); d_table is set to NULL. */
+int amber_weibull_from_coeffs(double a_w, double b_w, double c_w, amber_weibull* out);
+
+/* Writes the T + 1 inversion-table values X_j into host_table (n_entries must
+ * equal w->table_n).  The caller copies them to the device and sets d_table. */
+int amber_weibull_table(const amber_weibull* w, double* host_table, int64_t n_entries);
+
+/* ---- plans and workspace ------------------------------------------------ */
+
+/* Plan for an N^3 periodic box of side box_len (same length unit as l_mfp).
+ * N must be one of 8, 16, 32, 64, 96, 128, 192, 256, 512, 1024.  Allocates the
+ * plan's twiddle tables on the current device (the only allocation the library
+ * makes).  AMBER_E_SIZE for other N. */
+int amber_plan_create(amber_plan* out, int n, double box_len);
+void amber_plan_destroy(amber_plan plan);
+
+/* Device workspace needed by amber_radiation (with n_lmfp mean free paths),
+ * amber_rank and amber_zre on this plan. */
+size_t amber_workspace_bytes(amber_plan plan, int n_lmfp);
+
+/* ---- device stages ------------------------------------------------------ */
+
+/* Radiation field, Sec. 3.4.1 (Eq. intensity):
+ *   J_l = IDFT[ DFT(S) * Khat(|k|; l) ] / N^3,  Khat(k; l) = atan(k l)/k, Khat(0) = l,
+ *   k = (2 pi / box_len) |m~| with m~ the signed integer frequency.
+ * d_src: N^3 FP32 source field S (read only).  l_mfp: host array of n_lmfp
+ * mean free paths (> 0, finite).  d_J: host array of n_lmfp device pointers,
+ * each to N^3 FP32 outputs (must not alias d_src or the workspace).  The
+ * forward transform of S is computed once and shared by all l_mfp. */
+int amber_radiation(amber_plan plan, const float* d_src, const double* l_mfp, int n_lmfp,
+                    float* const* d_J, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Rank order of Sec. 3.4.2: d_perm[n] = index of the cell of rank n, ranking by
+ * d_J descending, ties by ascending cell index, -0 equal to +0.  NaN sets
+ * AMBER_STATUS_NAN_J.  d_perm: N^3 uint32 outputs. */
+int amber_rank(amber_plan plan, const float* d_J, uint32_t* d_perm,
+               void* d_ws, size_t ws_bytes, void* stream);
+
+/* Abundance matching, Sec. 3.4.2:
+ *   C_n = exact sum of d_w over the cells of rank <= n (inclusive),
+ *   F_n = RN(C_n) / RN(C_N)  (FP64, round-to-nearest-even conversions),
+ *   z_n = the table inversion of x_i(z) = F_n:
+ *         j = max{ j in [0, T] : X_j >= F_n } clamped to T - 1,
+ *         t = (X_j - F_n) / (X_j - X_{j+1})  (0 when the two are equal),
+ *         z = z_j + t (z_{j+1} - z_j),  z = min(z, z_top),
+ *         all in FP64 without fused multiply-add,
+ *   d_zre[h][perm[n]] = (float) z_n for each history h.
+ * d_J: N^3 FP32 intensities; d_w: N^3 FP32 gas-mass weights (1 + delta, > 0);
+ * hist: host array of n_hist fitted histories with device tables; d_zre: host
+ * array of n_hist device pointers to N^3 FP32 outputs.  The rank order and the
+ * cumulative mass are computed once and shared by all histories. */
+int amber_zre(amber_plan plan, const float* d_J, const float* d_w,
+              const amber_weibull* hist, int n_hist, float* const* d_zre,
+              void* d_ws, size_t ws_bytes, void* stream);
+
+/* Waits for `stream`, then returns (and clears) the device status bits of the
+ * last calls that used this workspace in *status. */
+int amber_status(amber_plan plan, void* d_ws, void* stream, unsigned* status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMBER_H */

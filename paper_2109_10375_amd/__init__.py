@@ -1,0 +1,21 @@
+"""MI355X (gfx950) library for the reionization-redshift hot path of AMBER.
+
+Trac et al., "AMBER: A Semi-numerical Abundance Matching Box for the Epoch of
+Reionization", arXiv:2109.10375.  The compute lives in ``libamber.so`` (HIP
+kernels behind the C-ABI in ``include/amber.h``); this package only marshals
+torch tensors, streams and structs into those calls.  There is no CPU path: if
+the library is missing, every call raises.
+"""
+from ._lib import (  # noqa: F401
+    AmberError,
+    History,
+    Plan,
+    STATUS_BAD_W,
+    STATUS_NAN_J,
+    STATUS_RANGE,
+    lib,
+    library_path,
+)
+
+__all__ = ["AmberError", "History", "Plan", "lib", "library_path",
+           "STATUS_NAN_J", "STATUS_BAD_W", "STATUS_RANGE"]

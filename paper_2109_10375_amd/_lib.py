@@ -1,0 +1,206 @@
+"""ctypes binding of libamber.so (argument marshalling only).
+
+Every method maps onto one C-ABI entry point of ``include/amber.h`` with the
+same name; tensors must already live on the GPU, and work is enqueued on
+torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libamber.so")
+
+OK = 0
+E_ARG, E_SIZE, E_HISTORY, E_WORKSPACE, E_HIP, E_UNIMPL = -1, -2, -3, -4, -5, -6
+STATUS_NAN_J, STATUS_BAD_W, STATUS_RANGE = 1, 2, 4
+
+SYMBOLS = [
+    "amber_version", "amber_strerror", "amber_weibull_fit", "amber_weibull_from_coeffs",
+    "amber_weibull_table", "amber_plan_create", "amber_plan_destroy", "amber_workspace_bytes",
+    "amber_radiation", "amber_rank", "amber_zre", "amber_status",
+]
+
+
+class AmberWeibull(ctypes.Structure):
+    _fields_ = [("a_w", ctypes.c_double), ("b_w", ctypes.c_double), ("c_w", ctypes.c_double),
+                ("h", ctypes.c_double), ("z_top", ctypes.c_double), ("table_n", ctypes.c_int64),
+                ("d_table", ctypes.c_void_p)]
+
+
+class AmberHistory(ctypes.Structure):
+    _fields_ = [("z_mid", ctypes.c_double), ("delta_z", ctypes.c_double), ("a_z", ctypes.c_double),
+                ("x_ear", ctypes.c_double), ("x_mid", ctypes.c_double), ("x_lat", ctypes.c_double)]
+
+
+class AmberError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        msg = lib().amber_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib() -> ctypes.CDLL:
+    """Load the in-tree HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, sz, i, d, i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_double, ctypes.c_int64
+        L.amber_version.restype = ctypes.c_char_p
+        L.amber_strerror.restype = ctypes.c_char_p
+        L.amber_strerror.argtypes = [i]
+        L.amber_weibull_fit.argtypes = [ctypes.POINTER(AmberHistory), ctypes.POINTER(AmberWeibull)]
+        L.amber_weibull_from_coeffs.argtypes = [d, d, d, ctypes.POINTER(AmberWeibull)]
+        L.amber_weibull_table.argtypes = [ctypes.POINTER(AmberWeibull), vp, i64]
+        L.amber_plan_create.argtypes = [ctypes.POINTER(vp), i, d]
+        L.amber_plan_destroy.argtypes = [vp]
+        L.amber_plan_destroy.restype = None
+        L.amber_workspace_bytes.argtypes = [vp, i]
+        L.amber_workspace_bytes.restype = sz
+        L.amber_radiation.argtypes = [vp, vp, ctypes.POINTER(d), i, ctypes.POINTER(vp), vp, sz, vp]
+        L.amber_rank.argtypes = [vp, vp, vp, vp, sz, vp]
+        L.amber_zre.argtypes = [vp, vp, vp, ctypes.POINTER(AmberWeibull), i, ctypes.POINTER(vp), vp, sz, vp]
+        L.amber_status.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_uint)]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != OK:
+        raise AmberError(rc, what)
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor, dtype: torch.dtype, numel: int, what: str) -> ctypes.c_void_p:
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{what}: expected a contiguous CUDA {dtype} tensor of {numel} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class History:
+    """A reionization history (Sec. 3.1): Weibull coefficients + device table."""
+
+    def __init__(self, w: AmberWeibull, device=None):
+        self.w = w
+        host = torch.empty(w.table_n, dtype=torch.float64)
+        _check(lib().amber_weibull_table(ctypes.byref(w), ctypes.c_void_p(host.data_ptr()), w.table_n),
+               "amber_weibull_table")
+        self.table = host.to(device or torch.device("cuda"))
+        self.w.d_table = self.table.data_ptr()
+
+    @classmethod
+    def from_params(cls, z_mid, delta_z, a_z, x_ear=0.0, x_mid=0.0, x_lat=0.0, device=None):
+        h = AmberHistory(z_mid, delta_z, a_z, x_ear, x_mid, x_lat)
+        w = AmberWeibull()
+        _check(lib().amber_weibull_fit(ctypes.byref(h), ctypes.byref(w)), "amber_weibull_fit")
+        return cls(w, device)
+
+    @classmethod
+    def from_coeffs(cls, a_w, b_w, c_w, device=None):
+        w = AmberWeibull()
+        _check(lib().amber_weibull_from_coeffs(a_w, b_w, c_w, ctypes.byref(w)), "amber_weibull_from_coeffs")
+        return cls(w, device)
+
+    @staticmethod
+    def fit_host(z_mid, delta_z, a_z, x_ear=0.0, x_mid=0.0, x_lat=0.0) -> AmberWeibull:
+        """The library's host-side fit without touching the GPU."""
+        h = AmberHistory(z_mid, delta_z, a_z, x_ear, x_mid, x_lat)
+        w = AmberWeibull()
+        _check(lib().amber_weibull_fit(ctypes.byref(h), ctypes.byref(w)), "amber_weibull_fit")
+        return w
+
+    @property
+    def coeffs(self):
+        return self.w.a_w, self.w.b_w, self.w.c_w
+
+
+class Plan:
+    """An N^3 periodic box of side box_len on the current GPU (amber_plan_create)."""
+
+    def __init__(self, n: int, box_len: float):
+        self.n = int(n)
+        self.box_len = float(box_len)
+        self.n3 = self.n ** 3
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        h = ctypes.c_void_p()
+        _check(lib().amber_plan_create(ctypes.byref(h), self.n, self.box_len), "amber_plan_create")
+        self._h = h
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.amber_plan_destroy(h)
+            self._h = None
+
+    def workspace_bytes(self, n_lmfp: int = 1) -> int:
+        return int(lib().amber_workspace_bytes(self._h, int(n_lmfp)))
+
+    def workspace(self, n_lmfp: int = 1) -> torch.Tensor:
+        need = self.workspace_bytes(n_lmfp)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            torch.cuda.empty_cache()
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def radiation(self, S: torch.Tensor, l_mfp: Sequence[float], out: Sequence[torch.Tensor] | None = None):
+        """amber_radiation: one J field per mean free path."""
+        l = [float(x) for x in l_mfp]
+        if out is None:
+            out = [torch.empty((self.n,) * 3, dtype=torch.float32, device=self.device) for _ in l]
+        src = _dev_ptr(S, torch.float32, self.n3, "S")
+        ptrs = (ctypes.c_void_p * len(l))(*[_dev_ptr(o, torch.float32, self.n3, "J").value for o in out])
+        larr = (ctypes.c_double * len(l))(*l)
+        ws = self.workspace(len(l))
+        _check(lib().amber_radiation(self._h, src, larr, len(l), ptrs, ctypes.c_void_p(ws.data_ptr()),
+                                     ws.numel(), _stream()), "amber_radiation")
+        return list(out)
+
+    def rank(self, J: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """amber_rank: the descending rank order (uint32 stored in an int32 tensor)."""
+        if out is None:
+            out = torch.empty(self.n3, dtype=torch.int32, device=self.device)
+        ws = self.workspace(1)
+        _check(lib().amber_rank(self._h, _dev_ptr(J, torch.float32, self.n3, "J"),
+                                _dev_ptr(out, torch.int32, self.n3, "perm"), ctypes.c_void_p(ws.data_ptr()),
+                                ws.numel(), _stream()), "amber_rank")
+        return out
+
+    def zre(self, J: torch.Tensor, w: torch.Tensor, hists: Sequence[History],
+            out: Sequence[torch.Tensor] | None = None):
+        """amber_zre: one z_re field per history."""
+        if out is None:
+            out = [torch.empty((self.n,) * 3, dtype=torch.float32, device=self.device) for _ in hists]
+        harr = (AmberWeibull * len(hists))(*[h.w for h in hists])
+        ptrs = (ctypes.c_void_p * len(hists))(*[_dev_ptr(o, torch.float32, self.n3, "z_re").value for o in out])
+        ws = self.workspace(1)
+        _check(lib().amber_zre(self._h, _dev_ptr(J, torch.float32, self.n3, "J"),
+                               _dev_ptr(w, torch.float32, self.n3, "w"), harr, len(hists), ptrs,
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "amber_zre")
+        return list(out)
+
+    def status(self) -> int:
+        """amber_status: device status bits of the last ranking/matching call."""
+        v = ctypes.c_uint()
+        ws = self.workspace(1)
+        _check(lib().amber_status(self._h, ctypes.c_void_p(ws.data_ptr()), _stream(), ctypes.byref(v)),
+               "amber_status")
+        return int(v.value)

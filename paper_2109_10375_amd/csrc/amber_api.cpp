@@ -1,0 +1,285 @@
+// Host side of the C-ABI: argument checks, plans, workspace layout, the
+// reionization-history fit (Sec. 3.1, Appendix A) and the inversion table.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace {
+
+bool supported_n(int n) {
+    switch (n) {
+        case 8: case 16: case 32: case 64: case 96: case 128: case 192: case 256: case 512: case 1024:
+            return true;
+        default:
+            return false;
+    }
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// g(c) = (p_e - p_m) - A_z (p_m - p_l) with p = |ln x|^(1/c): zero exactly when
+// the Weibull curve through the mid and late points also passes the early one
+// (Eqs. (asymmetry), (weibull)); positive for small c, negative for large c.
+double asym_residual(double c, double le, double lm, double ll, double az) {
+    const double pe = std::pow(le, 1.0 / c), pm = std::pow(lm, 1.0 / c), pl = std::pow(ll, 1.0 / c);
+    return (pe - pm) - az * (pm - pl);
+}
+
+// Brent's method on s = ln c over a sign-change bracket.
+bool solve_c(double le, double lm, double ll, double az, double* c_out) {
+    double a = std::log(1.0 / 64.0), b = std::log(4096.0);
+    double fa = asym_residual(std::exp(a), le, lm, ll, az), fb = asym_residual(std::exp(b), le, lm, ll, az);
+    if (!(fa > 0.0) || !(fb < 0.0)) {
+        // narrow the upper end: the residual tends to 0- only slowly
+        return false;
+    }
+    double c = a, fc = fa, d = b - a, e = d;
+    for (int it = 0; it < 300; ++it) {
+        if ((fb > 0.0) == (fc > 0.0)) {
+            c = a; fc = fa; d = b - a; e = d;
+        }
+        if (std::fabs(fc) < std::fabs(fb)) {
+            a = b; b = c; c = a;
+            fa = fb; fb = fc; fc = fa;
+        }
+        const double tol = 2.0 * 2.220446049250313e-16 * std::fabs(b) + 1e-300;
+        const double m = 0.5 * (c - b);
+        if (std::fabs(m) <= tol || fb == 0.0) break;
+        if (std::fabs(e) >= tol && std::fabs(fa) > std::fabs(fb)) {
+            double p, q, r;
+            const double s = fb / fa;
+            if (a == c) {
+                p = 2.0 * m * s;
+                q = 1.0 - s;
+            } else {
+                q = fa / fc;
+                r = fb / fc;
+                p = s * (2.0 * m * q * (q - r) - (b - a) * (r - 1.0));
+                q = (q - 1.0) * (r - 1.0) * (s - 1.0);
+            }
+            if (p > 0.0) q = -q; else p = -p;
+            if (2.0 * p < std::min(3.0 * m * q - std::fabs(tol * q), std::fabs(e * q))) {
+                e = d;
+                d = p / q;
+            } else {
+                d = m;
+                e = d;
+            }
+        } else {
+            d = m;
+            e = d;
+        }
+        a = b;
+        fa = fb;
+        b += (std::fabs(d) > tol) ? d : (m > 0 ? tol : -tol);
+        fb = asym_residual(std::exp(b), le, lm, ll, az);
+    }
+    *c_out = std::exp(b);
+    return std::isfinite(*c_out);
+}
+
+}  // namespace
+
+WsLayout ws_layout(int n, int n_lmfp) {
+    WsLayout L{};
+    const size_t N = (size_t)n, n3 = N * N * N;
+    const size_t n_tiles = (n3 + 4095) / 4096;
+    size_t off = 0;
+    L.ctrl = off;
+    off = align256(off + sizeof(Ctrl));
+    const size_t region = off;
+    // radiation
+    size_t f = region;
+    L.spec_a = f; f = align256(f + N * N * (N / 2) * sizeof(float2));
+    L.nyq_a = f;  f = align256(f + N * N * sizeof(float2));
+    if (n_lmfp > 1) {
+        L.spec_b = f; f = align256(f + N * N * (N / 2) * sizeof(float2));
+        L.nyq_b = f;  f = align256(f + N * N * sizeof(float2));
+    } else {
+        L.spec_b = L.spec_a;
+        L.nyq_b = L.nyq_a;
+    }
+    // ranking and matching (same region: the stages never overlap on a stream)
+    size_t r = region;
+    for (int i = 0; i < 2; ++i) { L.keys[i] = r; r = align256(r + n3 * 4); }
+    for (int i = 0; i < 2; ++i) { L.vals[i] = r; r = align256(r + n3 * 4); }
+    for (int i = 0; i < 2; ++i) { L.wts[i] = r; r = align256(r + n3 * 4); }
+    L.lookback = r;
+    r = align256(r + n_tiles * 256 * 4 * 2 + n_tiles * 16);
+    L.total = std::max(f, r);
+    return L;
+}
+
+extern "C" {
+
+const char* amber_version(void) { return "amber-mi355x 0.1 (gfx950)"; }
+
+const char* amber_strerror(int code) {
+    switch (code) {
+        case AMBER_OK: return "ok";
+        case AMBER_E_ARG: return "invalid argument";
+        case AMBER_E_SIZE: return "unsupported grid size";
+        case AMBER_E_HISTORY: return "no valid Weibull history for these parameters";
+        case AMBER_E_WORKSPACE: return "workspace too small";
+        case AMBER_E_HIP: return "HIP runtime error";
+        case AMBER_E_UNIMPL: return "not implemented";
+        default: return "unknown error";
+    }
+}
+
+int amber_weibull_from_coeffs(double a_w, double b_w, double c_w, amber_weibull* out) {
+    if (!out) return AMBER_E_ARG;
+    if (!(a_w > 0.0) || !(b_w > 0.0) || !(c_w > 0.0) || !std::isfinite(a_w) || !std::isfinite(b_w) ||
+        !std::isfinite(c_w))
+        return AMBER_E_HISTORY;
+    const double top = a_w + b_w * std::pow(64.0 * 0.69314718055994530942, 1.0 / c_w);
+    const double span = top - a_w;
+    const double r = span / 4194304.0;
+    int e = 0;
+    const double f = std::frexp(r, &e);
+    const double h = (f == 0.5) ? r : std::ldexp(1.0, e);
+    out->a_w = a_w;
+    out->b_w = b_w;
+    out->c_w = c_w;
+    out->h = h;
+    out->z_top = top;
+    out->table_n = (int64_t)std::ceil(span / h) + 1;
+    out->d_table = nullptr;
+    return AMBER_OK;
+}
+
+int amber_weibull_fit(const amber_history* hist, amber_weibull* out) {
+    if (!hist || !out) return AMBER_E_ARG;
+    const double xe = hist->x_ear == 0.0 ? 0.05 : hist->x_ear;
+    const double xm = hist->x_mid == 0.0 ? 0.5 : hist->x_mid;
+    const double xl = hist->x_lat == 0.0 ? 0.95 : hist->x_lat;
+    if (!(0.0 < xe && xe < xm && xm < xl && xl < 1.0)) return AMBER_E_ARG;
+    if (!std::isfinite(hist->z_mid) || !(hist->delta_z > 0.0) || !(hist->a_z > 0.0) || !std::isfinite(hist->delta_z) ||
+        !std::isfinite(hist->a_z))
+        return AMBER_E_ARG;
+    if (hist->a_z > 15.0) return AMBER_E_HISTORY;
+    // Sec. 3.1.1: the early and late points
+    const double z_ear = hist->z_mid + hist->delta_z * hist->a_z / (1.0 + hist->a_z);
+    const double z_lat = z_ear - hist->delta_z;
+    const double le = std::fabs(std::log(xe)), lm = std::fabs(std::log(xm)), ll = std::fabs(std::log(xl));
+    double c = 0.0;
+    if (!solve_c(le, lm, ll, hist->a_z, &c)) return AMBER_E_HISTORY;
+    // Appendix A: the two algebraic coefficients
+    const double pe = std::pow(le, 1.0 / c), pm = std::pow(lm, 1.0 / c), pl = std::pow(ll, 1.0 / c);
+    const double a = (z_ear * pl - z_lat * pe) / (pl - pe);
+    const double b = (hist->z_mid - a) / pm;
+    return amber_weibull_from_coeffs(a, b, c, out);
+}
+
+int amber_weibull_table(const amber_weibull* w, double* host_table, int64_t n_entries) {
+    if (!w || !host_table || n_entries != w->table_n || n_entries < 2) return AMBER_E_ARG;
+    const double a = w->a_w, b = w->b_w, c = w->c_w, h = w->h;
+    for (int64_t j = 0; j < n_entries; ++j) {
+        const double z = a + (double)j * h;
+        host_table[j] = std::exp(-std::pow((z - a) / b, c));
+    }
+    return AMBER_OK;
+}
+
+int amber_plan_create(amber_plan* out, int n, double box_len) {
+    if (!out) return AMBER_E_ARG;
+    *out = nullptr;
+    if (!supported_n(n)) return AMBER_E_SIZE;
+    if (!(box_len > 0.0) || !std::isfinite(box_len)) return AMBER_E_ARG;
+    amber_plan_s* p = new (std::nothrow) amber_plan_s();
+    if (!p) return AMBER_E_ARG;
+    p->n = n;
+    p->box_len = box_len;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return AMBER_E_HIP;
+    }
+    float2* host = new (std::nothrow) float2[n];
+    if (!host) {
+        delete p;
+        return AMBER_E_ARG;
+    }
+    for (int j = 0; j < n; ++j) {
+        // exp(-2 pi i j / n) from long-double (64-bit significand) cos/sin
+        const long double t = 2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)n;
+        host[j] = make_float2((float)cosl(t), (float)(-sinl(t)));
+    }
+    hipError_t e = hipMalloc(&p->d_tw, sizeof(float2) * (size_t)n);
+    if (e == hipSuccess) e = hipMemcpy(p->d_tw, host, sizeof(float2) * (size_t)n, hipMemcpyHostToDevice);
+    delete[] host;
+    if (e != hipSuccess) {
+        if (p->d_tw) (void)hipFree(p->d_tw);
+        delete p;
+        return AMBER_E_HIP;
+    }
+    *out = p;
+    return AMBER_OK;
+}
+
+void amber_plan_destroy(amber_plan plan) {
+    if (!plan) return;
+    if (plan->d_tw) (void)hipFree(plan->d_tw);
+    delete plan;
+}
+
+size_t amber_workspace_bytes(amber_plan plan, int n_lmfp) {
+    if (!plan) return 0;
+    return ws_layout(plan->n, n_lmfp < 1 ? 1 : n_lmfp).total;
+}
+
+int amber_radiation(amber_plan plan, const float* d_src, const double* l_mfp, int n_lmfp, float* const* d_J,
+                    void* d_ws, size_t ws_bytes, void* stream) {
+    if (!plan || !d_src || !l_mfp || !d_J || !d_ws || n_lmfp < 1 || n_lmfp > 64) return AMBER_E_ARG;
+    for (int i = 0; i < n_lmfp; ++i) {
+        if (!(l_mfp[i] > 0.0) || !std::isfinite(l_mfp[i]) || !d_J[i]) return AMBER_E_ARG;
+        if ((const void*)d_J[i] == (const void*)d_src) return AMBER_E_ARG;
+    }
+    const WsLayout L = ws_layout(plan->n, n_lmfp);
+    if (ws_bytes < L.total) return AMBER_E_WORKSPACE;
+    return fft_radiation(plan, d_src, l_mfp, n_lmfp, d_J, static_cast<unsigned char*>(d_ws), L,
+                         static_cast<hipStream_t>(stream));
+}
+
+int amber_rank(amber_plan plan, const float* d_J, uint32_t* d_perm, void* d_ws, size_t ws_bytes, void* stream) {
+    if (!plan || !d_J || !d_perm || !d_ws) return AMBER_E_ARG;
+    const WsLayout L = ws_layout(plan->n, 1);
+    if (ws_bytes < L.total) return AMBER_E_WORKSPACE;
+    return rank_sort(plan, d_J, nullptr, static_cast<unsigned char*>(d_ws), L, static_cast<hipStream_t>(stream), 0,
+                     d_perm);
+}
+
+int amber_zre(amber_plan plan, const float* d_J, const float* d_w, const amber_weibull* hist, int n_hist,
+              float* const* d_zre, void* d_ws, size_t ws_bytes, void* stream) {
+    if (!plan || !d_J || !d_w || !hist || !d_zre || !d_ws || n_hist < 1 || n_hist > 8) return AMBER_E_ARG;
+    for (int i = 0; i < n_hist; ++i) {
+        const amber_weibull& w = hist[i];
+        if (!d_zre[i] || !w.d_table || w.table_n < 2) return AMBER_E_ARG;
+        if (!(w.a_w > 0.0) || !(w.b_w > 0.0) || !(w.c_w > 0.0) || !(w.h > 0.0) || !(w.z_top > w.a_w) ||
+            !std::isfinite(w.z_top))
+            return AMBER_E_HISTORY;
+    }
+    const WsLayout L = ws_layout(plan->n, 1);
+    if (ws_bytes < L.total) return AMBER_E_WORKSPACE;
+    unsigned char* ws = static_cast<unsigned char*>(d_ws);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = rank_sort(plan, d_J, d_w, ws, L, s, 1, nullptr);
+    if (rc != AMBER_OK) return rc;
+    return match_scan(plan, hist, n_hist, d_zre, ws, L, s);
+}
+
+int amber_status(amber_plan plan, void* d_ws, void* stream, unsigned* status) {
+    if (!plan || !d_ws || !status) return AMBER_E_ARG;
+    const WsLayout L = ws_layout(plan->n, 1);
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(static_cast<unsigned char*>(d_ws) + L.ctrl);
+    AMBER_HIP_CHECK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    unsigned v = 0, zero = 0;
+    AMBER_HIP_CHECK(hipMemcpy(&v, &ctrl->status, sizeof(unsigned), hipMemcpyDeviceToHost));
+    AMBER_HIP_CHECK(hipMemcpy(&ctrl->status, &zero, sizeof(unsigned), hipMemcpyHostToDevice));
+    *status = v;
+    return AMBER_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,434 @@
+// Radiation field on gfx950: J = IDFT[ DFT(S) * atan(k l)/k ] / N^3 (Sec. 3.4.1,
+// Eq. intensity, evaluated as a periodic convolution through FFTs).
+//
+// Spectrum layout (device workspace, complex FP32):
+//   main[x][y][kz] for kz in [0, N/2)   (row pitch N/2, 256-byte aligned rows)
+//   nyq[x][y]      for kz = N/2          (the real-input Nyquist plane)
+// Five streaming passes per l_mfp, each reading and writing the array once:
+//   1. z  : real-to-complex along the contiguous axis (lines of N reals)
+//   2. y  : complex FFT down columns of the (x, kz) planes, tiles of C columns
+//   3. x  : forward FFT, multiply by Khat/N^3, inverse FFT, in one kernel
+//   4. y  : inverse
+//   5. z  : complex-to-real
+// Every length-L transform inside a pass is split L = L1 x L2 over L1 threads:
+// each thread does an L2-point DFT in registers on a decimated subsequence,
+// applies the inter-step twiddles, exchanges through LDS (padded against bank
+// conflicts), and finishes with L1-point DFTs in registers.  A thread ends up
+// holding the same element positions it loaded, so every pass reads and writes
+// with the same coalesced pattern.  Twiddles come from an FP64-generated table;
+// the in-register DFT constants are exact compile-time values.
+#include <cmath>
+
+#include "internal.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Compile-time roots of unity: cos/sin(2 pi m / R) with the quadrant removed
+// exactly in integers and a Taylor series on |r| <= pi/4.
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double taylor_sin(double x) {
+    double x2 = x * x, term = x, sum = x;
+    for (int k = 1; k < 14; ++k) {
+        term *= -x2 / double((2 * k) * (2 * k + 1));
+        sum += term;
+    }
+    return sum;
+}
+
+constexpr double taylor_cos(double x) {
+    double x2 = x * x, term = 1.0, sum = 1.0;
+    for (int k = 1; k < 14; ++k) {
+        term *= -x2 / double((2 * k - 1) * (2 * k));
+        sum += term;
+    }
+    return sum;
+}
+
+struct Root {
+    double c, s;
+};
+
+constexpr Root root_of_unity(long m, long R) {
+    m %= R;
+    if (m < 0) m += R;
+    long q = (8 * m + R) / (2 * R);  // nearest multiple of pi/2
+    long rn = 4 * m - q * R;         // |rn| <= R/2
+    double r = (kPi / 2.0) * double(rn) / double(R);
+    double c = taylor_cos(r), s = taylor_sin(r);
+    switch (q & 3) {
+        case 0: return Root{c, s};
+        case 1: return Root{-s, c};
+        case 2: return Root{-c, -s};
+        default: return Root{s, -c};
+    }
+}
+
+template <int R>
+struct RootTable {
+    float c[R];
+    float s[R];
+    constexpr RootTable() : c(), s() {
+        for (int m = 0; m < R; ++m) {
+            Root t = root_of_unity(m, R);
+            c[m] = float(t.c);
+            s[m] = float(t.s);
+        }
+    }
+};
+
+template <int R>
+__device__ constexpr RootTable<R> kRoots = RootTable<R>();
+
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 mul_mi(float2 v) {
+    return INV ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
+}
+
+// v * W_R^e with W_R = exp(-2 pi i / R) (forward) or its conjugate (inverse);
+// e is a compile-time constant after unrolling.
+template <int R, bool INV>
+__device__ __forceinline__ float2 twc(float2 v, int e) {
+    e %= R;
+    if (e == 0) return v;
+    if (4 * e == R) return mul_mi<INV>(v);
+    if (2 * e == R) return make_float2(-v.x, -v.y);
+    if (4 * e == 3 * R) return mul_mi<!INV>(v);
+    const float c = kRoots<R>.c[e];
+    const float s = INV ? kRoots<R>.s[e] : -kRoots<R>.s[e];
+    return make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
+}
+
+// In-register DFT of R points, natural order in and out.
+template <int R>
+struct Split {  // R = A * B
+    static constexpr int A = R == 6 ? 2 : R == 8 ? 4 : R == 12 ? 4 : R == 16 ? 4 : R == 24 ? 8 : R == 32 ? 8 : 0;
+    static constexpr int B = A ? R / A : 0;
+};
+
+template <int R, bool INV>
+struct Dft {
+    __device__ __forceinline__ static void run(float2* x) {
+        constexpr int A = Split<R>::A, B = Split<R>::B;
+        static_assert(A * B == R && A > 1, "unsupported in-register DFT size");
+        float2 t[R];
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+            float2 col[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) col[b] = x[a + A * b];
+            Dft<B, INV>::run(col);
+#pragma unroll
+            for (int kb = 0; kb < B; ++kb) t[a * B + kb] = twc<R, INV>(col[kb], a * kb);
+        }
+#pragma unroll
+        for (int kb = 0; kb < B; ++kb) {
+            float2 row[A];
+#pragma unroll
+            for (int a = 0; a < A; ++a) row[a] = t[a * B + kb];
+            Dft<A, INV>::run(row);
+#pragma unroll
+            for (int ka = 0; ka < A; ++ka) x[kb + B * ka] = row[ka];
+        }
+    }
+};
+
+template <bool INV>
+struct Dft<1, INV> {
+    __device__ __forceinline__ static void run(float2*) {}
+};
+
+template <bool INV>
+struct Dft<2, INV> {
+    __device__ __forceinline__ static void run(float2* x) {
+        float2 a = x[0], b = x[1];
+        x[0] = cadd(a, b);
+        x[1] = csub(a, b);
+    }
+};
+
+template <bool INV>
+struct Dft<3, INV> {
+    __device__ __forceinline__ static void run(float2* x) {
+        const float h = 0.8660254037844386f;  // sin(2 pi / 3)
+        float2 s = cadd(x[1], x[2]);
+        float2 d = csub(x[1], x[2]);
+        float2 m = make_float2(x[0].x - 0.5f * s.x, x[0].y - 0.5f * s.y);
+        float2 r = mul_mi<INV>(cscale(d, h));  // -i h d forward
+        x[0] = cadd(x[0], s);
+        x[1] = cadd(m, r);
+        x[2] = csub(m, r);
+    }
+};
+
+template <bool INV>
+struct Dft<4, INV> {
+    __device__ __forceinline__ static void run(float2* x) {
+        float2 a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
+        float2 c = cadd(x[1], x[3]), d = mul_mi<INV>(csub(x[1], x[3]));
+        x[0] = cadd(a, c);
+        x[2] = csub(a, c);
+        x[1] = cadd(b, d);
+        x[3] = csub(b, d);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// One length-L transform spread over L1 threads, L2 = L / L1 elements each,
+// L1 | L2.  On entry v[j] = x[t + L1 j]; on exit v[j] = X[t + L1 j].
+// lds points at this transform's LDS region: element (n1, k2) lives at
+// lds[n1 * SN1 + k2 * SK2].  tw is the table of exp(-2 pi i j / (L * TS)).
+template <int L, int L1, bool INV, int TS, int SN1, int SK2>
+__device__ __forceinline__ void fft_2step(float2* v, int t, float2* lds, const float2* __restrict__ tw) {
+    constexpr int L2 = L / L1;
+    constexpr int RR = L2 / L1;
+    static_assert(L1 * L2 == L && RR * L1 == L2, "bad split");
+    Dft<L2, INV>::run(v);
+#pragma unroll
+    for (int k2 = 1; k2 < L2; ++k2) {
+        float2 w = tw[(t * k2) * TS];
+        if (INV) w.y = -w.y;
+        v[k2] = cmul(v[k2], w);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k2 = 0; k2 < L2; ++k2) lds[t * SN1 + k2 * SK2] = v[k2];
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < RR; ++b) {
+        const int k2 = t + L1 * b;
+        float2 u[L1];
+#pragma unroll
+        for (int n1 = 0; n1 < L1; ++n1) u[n1] = lds[n1 * SN1 + k2 * SK2];
+        Dft<L1, INV>::run(u);
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1) v[b + RR * k1] = u[k1];
+    }
+}
+
+// Per-N launch shapes.
+//   column passes : L = N split N1 x N2, tiles of C columns, C * N1 threads
+//   z passes      : M = N/2 split M1 x M2, ZL lines per block, ZL * M1 threads
+template <int N>
+struct Shape;
+template <> struct Shape<8>    { static constexpr int N1 = 2,  C = 4,  M1 = 2,  ZL = 64; };
+template <> struct Shape<16>   { static constexpr int N1 = 4,  C = 8,  M1 = 2,  ZL = 64; };
+template <> struct Shape<32>   { static constexpr int N1 = 4,  C = 16, M1 = 4,  ZL = 64; };
+template <> struct Shape<64>   { static constexpr int N1 = 8,  C = 32, M1 = 4,  ZL = 64; };
+template <> struct Shape<96>   { static constexpr int N1 = 4,  C = 16, M1 = 4,  ZL = 64; };
+template <> struct Shape<128>  { static constexpr int N1 = 8,  C = 32, M1 = 8,  ZL = 32; };
+template <> struct Shape<192>  { static constexpr int N1 = 8,  C = 32, M1 = 4,  ZL = 64; };
+template <> struct Shape<256>  { static constexpr int N1 = 16, C = 16, M1 = 8,  ZL = 32; };
+template <> struct Shape<512>  { static constexpr int N1 = 16, C = 16, M1 = 16, ZL = 16; };
+template <> struct Shape<1024> { static constexpr int N1 = 32, C = 8,  M1 = 16, ZL = 16; };
+
+// Tile geometry of a column pass: element (row r, column c) of tile (ta, tb)
+// is at ta * sa + tb * sb + r * row + c * col (complex elements).
+struct ColGeom {
+    long long row, col, sa, sb;
+    int tiles_b;
+};
+
+struct MulArgs {
+    float k0;     // 2 pi / box_len
+    float lmfp;
+    float scale;  // 1 / N^3
+    int nyq;      // 1: the Nyquist plane (kz = N/2, columns are ky)
+};
+
+__device__ __forceinline__ int signed_freq(int m, int n) { return (2 * m <= n) ? m : m - n; }
+
+// Column pass.  MODE 0: one transform (INV selects the direction).
+// MODE 1: forward transform, multiply by Khat(|k|)/N^3, inverse transform.
+template <int N, int MODE, bool INV>
+__global__ __launch_bounds__(Shape<N>::C * Shape<N>::N1) void k_fft_cols(
+    const float2* __restrict__ in, float2* __restrict__ out, const float2* __restrict__ tw,
+    ColGeom g, MulArgs m) {
+    constexpr int N1 = Shape<N>::N1, C = Shape<N>::C, N2 = N / N1;
+    __shared__ float2 lds[N1 * (N2 + 1) * C];
+    const int tid = threadIdx.x;
+    const int c = tid % C, t = tid / C;
+    const int tb = blockIdx.x % g.tiles_b, ta = blockIdx.x / g.tiles_b;
+    const long long base = (long long)ta * g.sa + (long long)tb * g.sb + (long long)c * g.col;
+    float2 v[N2];
+#pragma unroll
+    for (int j = 0; j < N2; ++j) v[j] = in[base + (long long)(t + N1 * j) * g.row];
+    float2* col = lds + c;
+    if (MODE == 0) {
+        fft_2step<N, N1, INV, 1, (N2 + 1) * C, C>(v, t, col, tw);
+    } else {
+        fft_2step<N, N1, false, 1, (N2 + 1) * C, C>(v, t, col, tw);
+        int my, mz;
+        if (m.nyq) {
+            my = tb * C + c;
+            mz = N / 2;
+        } else {
+            my = ta;
+            mz = tb * C + c;
+        }
+        const int sy = signed_freq(my, N), sz = mz;
+        const int s2yz = sy * sy + sz * sz;
+#pragma unroll
+        for (int j = 0; j < N2; ++j) {
+            const int sx = signed_freq(t + N1 * j, N);
+            const float kk = m.k0 * sqrtf((float)(sx * sx + s2yz));
+            const float K = (kk > 0.0f) ? atanf(kk * m.lmfp) / kk : m.lmfp;
+            v[j] = cscale(v[j], K * m.scale);
+        }
+        fft_2step<N, N1, true, 1, (N2 + 1) * C, C>(v, t, col, tw);
+    }
+#pragma unroll
+    for (int j = 0; j < N2; ++j) out[base + (long long)(t + N1 * j) * g.row] = v[j];
+}
+
+// z pass, real to complex: N reals per line -> N/2 + 1 complex (N/2 in main,
+// the Nyquist value in nyq).  Packs x[2n] + i x[2n+1], does an N/2-point FFT
+// and separates even and odd halves:
+//   X[k] = (Z[k] + conj Z[M-k])/2 - i W_N^k (Z[k] - conj Z[M-k])/2.
+template <int N>
+__global__ __launch_bounds__(Shape<N>::ZL * Shape<N>::M1) void k_fft_z_r2c(
+    const float* __restrict__ src, float2* __restrict__ main_out, float2* __restrict__ nyq_out,
+    const float2* __restrict__ tw, long long n_lines) {
+    constexpr int M = N / 2, M1 = Shape<N>::M1, M2 = M / M1, ZL = Shape<N>::ZL;
+    constexpr int LS = M1 * (M2 + 1);  // per-line LDS stride (>= M + 1)
+    __shared__ float2 lds[ZL * LS];
+    const int tid = threadIdx.x;
+    const int t = tid % M1, l = tid / M1;
+    const long long line = (long long)blockIdx.x * ZL + l;
+    const bool live = line < n_lines;
+    const float2* row = reinterpret_cast<const float2*>(src + (live ? line : 0) * N);
+    float2 v[M2];
+#pragma unroll
+    for (int j = 0; j < M2; ++j) v[j] = live ? row[t + M1 * j] : make_float2(0.f, 0.f);
+    float2* mine = lds + l * LS;
+    fft_2step<M, M1, false, 2, M2 + 1, 1>(v, t, mine, tw);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < M2; ++j) mine[t + M1 * j] = v[j];
+    __syncthreads();
+    float2* orow = main_out + (live ? line : 0) * M;
+#pragma unroll
+    for (int j = 0; j < M2; ++j) {
+        const int k = t + M1 * j;
+        const float2 zk = mine[k];
+        const float2 zc = mine[(M - k) % M];
+        const float2 a = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
+        const float2 b = make_float2(0.5f * (zk.x - zc.x), 0.5f * (zk.y + zc.y));
+        const float2 wb = cmul(tw[k], b);
+        if (live) orow[k] = make_float2(a.x + wb.y, a.y - wb.x);
+    }
+    if (live && t == 0) {
+        const float2 z0 = mine[0];
+        nyq_out[line] = make_float2(z0.x - z0.y, 0.0f);
+    }
+}
+
+// z pass, complex to real (unnormalised inverse):
+//   Z'[k] = (X[k] + conj X[M-k]) + i W_N^-k (X[k] - conj X[M-k]),
+//   z = IDFT_M(Z'),  x[2n] = Re z[n], x[2n+1] = Im z[n].
+template <int N>
+__global__ __launch_bounds__(Shape<N>::ZL * Shape<N>::M1) void k_fft_z_c2r(
+    const float2* __restrict__ main_in, const float2* __restrict__ nyq_in, float* __restrict__ dst,
+    const float2* __restrict__ tw, long long n_lines) {
+    constexpr int M = N / 2, M1 = Shape<N>::M1, M2 = M / M1, ZL = Shape<N>::ZL;
+    constexpr int LS = M1 * (M2 + 1);
+    __shared__ float2 lds[ZL * LS];
+    const int tid = threadIdx.x;
+    const int t = tid % M1, l = tid / M1;
+    const long long line = (long long)blockIdx.x * ZL + l;
+    const bool live = line < n_lines;
+    const float2* irow = main_in + (live ? line : 0) * M;
+    float2* mine = lds + l * LS;
+#pragma unroll
+    for (int j = 0; j < M2; ++j) mine[t + M1 * j] = live ? irow[t + M1 * j] : make_float2(0.f, 0.f);
+    if (t == 0) mine[M] = live ? nyq_in[line] : make_float2(0.f, 0.f);
+    __syncthreads();
+    float2 v[M2];
+#pragma unroll
+    for (int j = 0; j < M2; ++j) {
+        const int k = t + M1 * j;
+        const float2 xk = mine[k];
+        const float2 xm = mine[M - k];
+        const float2 e = make_float2(xk.x + xm.x, xk.y - xm.y);   // X[k] + conj X[M-k]
+        const float2 d = make_float2(xk.x - xm.x, xk.y + xm.y);   // X[k] - conj X[M-k]
+        const float2 w = tw[k];
+        const float2 o = cmul(d, make_float2(w.x, -w.y));          // * W_N^-k
+        v[j] = make_float2(e.x - o.y, e.y + o.x);                  // e + i o
+    }
+    fft_2step<M, M1, true, 2, M2 + 1, 1>(v, t, mine, tw);
+    if (live) {
+        float2* orow = reinterpret_cast<float2*>(dst + line * N);
+#pragma unroll
+        for (int j = 0; j < M2; ++j) orow[t + M1 * j] = v[j];
+    }
+}
+
+template <int N>
+int run_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp, int n_lmfp,
+                  float* const* d_J, unsigned char* ws, const WsLayout& L, hipStream_t s) {
+    constexpr int H = N / 2, C = Shape<N>::C, N1 = Shape<N>::N1, ZL = Shape<N>::ZL, M1 = Shape<N>::M1;
+    static_assert(H % C == 0 && N % C == 0, "tile width must divide the spectrum rows");
+    const long long n_lines = (long long)N * N;
+    float2* spec_a = reinterpret_cast<float2*>(ws + L.spec_a);
+    float2* nyq_a = reinterpret_cast<float2*>(ws + L.nyq_a);
+    float2* spec_b = reinterpret_cast<float2*>(ws + L.spec_b);
+    float2* nyq_b = reinterpret_cast<float2*>(ws + L.nyq_b);
+    const float2* tw = p->d_tw;
+    const dim3 zblk(ZL * M1), cblk(C * N1);
+    const unsigned zgrid = (unsigned)((n_lines + ZL - 1) / ZL);
+
+    // geometry of the four kinds of column pass
+    const ColGeom y_main{H, 1, (long long)N * H, C, H / C};
+    const ColGeom y_nyq{1, N, 0, (long long)C * N, N / C};
+    const ColGeom x_main{(long long)N * H, 1, H, C, H / C};
+    const ColGeom x_nyq{N, 1, 0, C, N / C};
+    const unsigned g_main = (unsigned)N * (H / C), g_nyq = (unsigned)(N / C);
+    const MulArgs none{0.f, 0.f, 0.f, 0};
+
+    hipLaunchKernelGGL((k_fft_z_r2c<N>), dim3(zgrid), zblk, 0, s, d_src, spec_a, nyq_a, tw, n_lines);
+    hipLaunchKernelGGL((k_fft_cols<N, 0, false>), dim3(g_main), cblk, 0, s, spec_a, spec_a, tw, y_main, none);
+    hipLaunchKernelGGL((k_fft_cols<N, 0, false>), dim3(g_nyq), cblk, 0, s, nyq_a, nyq_a, tw, y_nyq, none);
+    for (int i = 0; i < n_lmfp; ++i) {
+        float2* so = (n_lmfp == 1) ? spec_a : spec_b;
+        float2* no = (n_lmfp == 1) ? nyq_a : nyq_b;
+        const float k0 = (float)(2.0 * kPi / p->box_len);
+        const float sc = (float)(1.0 / ((double)N * N * N));
+        const MulArgs mm{k0, (float)l_mfp[i], sc, 0};
+        const MulArgs mn{k0, (float)l_mfp[i], sc, 1};
+        hipLaunchKernelGGL((k_fft_cols<N, 1, false>), dim3(g_main), cblk, 0, s, spec_a, so, tw, x_main, mm);
+        hipLaunchKernelGGL((k_fft_cols<N, 1, false>), dim3(g_nyq), cblk, 0, s, nyq_a, no, tw, x_nyq, mn);
+        hipLaunchKernelGGL((k_fft_cols<N, 0, true>), dim3(g_main), cblk, 0, s, so, so, tw, y_main, none);
+        hipLaunchKernelGGL((k_fft_cols<N, 0, true>), dim3(g_nyq), cblk, 0, s, no, no, tw, y_nyq, none);
+        hipLaunchKernelGGL((k_fft_z_c2r<N>), dim3(zgrid), zblk, 0, s, so, no, d_J[i], tw, n_lines);
+    }
+    AMBER_HIP_CHECK(hipGetLastError());
+    return AMBER_OK;
+}
+
+}  // namespace
+
+int fft_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp, int n_lmfp,
+                  float* const* d_J, unsigned char* ws, const WsLayout& L, hipStream_t s) {
+    switch (p->n) {
+        case 8: return run_radiation<8>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
+        case 16: return run_radiation<16>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
+        case 32: return run_radiation<32>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
+        case 64: return run_radiation<64>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
+        case 96: return run_radiation<96>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
+        case 128: return run_radiation<128>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
+        case 192: return run_radiation<192>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
+        case 256: return run_radiation<256>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
+        case 512: return run_radiation<512>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
+        case 1024: return run_radiation<1024>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
+        default: return AMBER_E_SIZE;
+    }
+}

@@ -1,0 +1,62 @@
+// Internal declarations shared by the host API and the HIP kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/amber.h"
+
+struct amber_plan_s {
+    int n = 0;             // grid size per axis
+    double box_len = 0.0;  // box side
+    int device = -1;
+    float2* d_tw = nullptr;  // tw[j] = exp(-2 pi i j / n), j < n, FP64-rounded to FP32
+};
+
+// Byte layout of the caller's workspace for one plan.
+struct WsLayout {
+    size_t ctrl;        // control block (status, counters, histograms, totals)
+    size_t spec_a;      // N x N x N/2 complex spectrum
+    size_t nyq_a;       // N x N complex Nyquist plane (kz = N/2)
+    size_t spec_b;      // second spectrum (several l_mfp)
+    size_t nyq_b;
+    size_t keys[2];     // sort keys (ping-pong), N^3 uint32
+    size_t vals[2];     // cell indices, N^3 uint32
+    size_t wts[2];      // weights carried with the keys, N^3 float
+    size_t lookback;    // decoupled look-back tiles
+    size_t total;
+};
+
+WsLayout ws_layout(int n, int n_lmfp);
+
+// Control block (lives at offset 0 of the workspace; zeroed by a kernel at the
+// start of every matching call).
+struct Ctrl {
+    unsigned status;            // AMBER_STATUS_* bits (sticky until amber_status)
+    unsigned pad0;
+    unsigned tickets[8];        // tile tickets: 0-3 radix passes, 4 scan
+    unsigned hist[4][256];      // digit histograms of the descending keys
+    unsigned digit_off[4][256]; // exclusive prefix of hist
+    unsigned long long msum[256];  // per-FP32-exponent sums of significands of w
+    int qmin;                   // exponent of the smallest weight ulp (w = m 2^q)
+    int wide;                   // 1 when the total needs more than 64 bits
+    unsigned long long total_lo, total_hi;  // exact sum of w 2^-qmin
+};
+
+// FFT launches (fft.hip).
+int fft_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp, int n_lmfp,
+                  float* const* d_J, unsigned char* ws, const WsLayout& L, hipStream_t s);
+
+// Ranking and matching launches (rank.hip, match.hip).
+int rank_sort(const amber_plan_s* p, const float* d_J, const float* d_w, unsigned char* ws,
+              const WsLayout& L, hipStream_t s, int carry_weights, uint32_t* d_perm_out);
+int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, float* const* d_zre,
+               unsigned char* ws, const WsLayout& L, hipStream_t s);
+
+#define AMBER_HIP_CHECK(expr)                        \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return AMBER_E_HIP;    \
+    } while (0)
