@@ -153,6 +153,26 @@ int amber_zre(amber_plan plan, const float* d_J, const float* d_w,
  * last calls that used this workspace in *status. */
 int amber_status(amber_plan plan, void* d_ws, void* stream, unsigned* status);
 
+/* ---- per-kernel timing (tracing aid, not needed for results) ------------ */
+
+typedef struct {
+    char name[48];      /* kernel name, e.g. "fft_x_mul", "rank_pass1"          */
+    int32_t launches;   /* launches timed                                       */
+    double total_ms;    /* summed HIP-event time between each launch's start and
+                           stop events, recorded on the launch's own stream    */
+} amber_kernel_time;
+
+/* Starts timing the kernels that later compute calls on this plan launch:
+ * creates `capacity` pairs of HIP events (the only time the library creates
+ * events); launches beyond capacity are not timed.  Calls on several streams
+ * are timed each on its own stream. */
+int amber_profile_begin(amber_plan plan, int capacity);
+
+/* Waits for the recorded events, writes up to max_entries per-kernel totals
+ * (aggregated by name, in first-launch order) and their count, releases the
+ * events and stops timing. */
+int amber_profile_end(amber_plan plan, amber_kernel_time* out, int max_entries, int* n_entries);
+
 #ifdef __cplusplus
 }
 #endif

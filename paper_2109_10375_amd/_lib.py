@@ -22,7 +22,8 @@ STATUS_NAN_J, STATUS_BAD_W, STATUS_RANGE = 1, 2, 4
 SYMBOLS = [
     "amber_version", "amber_strerror", "amber_weibull_fit", "amber_weibull_from_coeffs",
     "amber_weibull_table", "amber_plan_create", "amber_plan_destroy", "amber_workspace_bytes",
-    "amber_radiation", "amber_rank", "amber_zre", "amber_status",
+    "amber_radiation", "amber_rank", "amber_zre", "amber_status", "amber_profile_begin",
+    "amber_profile_end",
 ]
 
 
@@ -30,6 +31,10 @@ class AmberWeibull(ctypes.Structure):
     _fields_ = [("a_w", ctypes.c_double), ("b_w", ctypes.c_double), ("c_w", ctypes.c_double),
                 ("h", ctypes.c_double), ("z_top", ctypes.c_double), ("table_n", ctypes.c_int64),
                 ("d_table", ctypes.c_void_p)]
+
+
+class AmberKernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int32), ("total_ms", ctypes.c_double)]
 
 
 class AmberHistory(ctypes.Structure):
@@ -75,6 +80,8 @@ def lib() -> ctypes.CDLL:
         L.amber_rank.argtypes = [vp, vp, vp, vp, sz, vp]
         L.amber_zre.argtypes = [vp, vp, vp, ctypes.POINTER(AmberWeibull), i, ctypes.POINTER(vp), vp, sz, vp]
         L.amber_status.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_uint)]
+        L.amber_profile_begin.argtypes = [vp, i]
+        L.amber_profile_end.argtypes = [vp, ctypes.POINTER(AmberKernelTime), i, ctypes.POINTER(i)]
         _lib = L
     return _lib
 
@@ -196,6 +203,17 @@ class Plan:
                                _dev_ptr(w, torch.float32, self.n3, "w"), harr, len(hists), ptrs,
                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "amber_zre")
         return list(out)
+
+    def profile_begin(self, capacity: int = 4096) -> None:
+        """amber_profile_begin: time every kernel of the following calls."""
+        _check(lib().amber_profile_begin(self._h, int(capacity)), "amber_profile_begin")
+
+    def profile_end(self) -> dict:
+        """amber_profile_end: {kernel name: (launches, total ms)}."""
+        buf = (AmberKernelTime * 64)()
+        n = ctypes.c_int()
+        _check(lib().amber_profile_end(self._h, buf, 64, ctypes.byref(n)), "amber_profile_end")
+        return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(n.value)}
 
     def status(self) -> int:
         """amber_status: device status bits of the last ranking/matching call."""

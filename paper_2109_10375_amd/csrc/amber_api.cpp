@@ -219,10 +219,76 @@ int amber_plan_create(amber_plan* out, int n, double box_len) {
     return AMBER_OK;
 }
 
+static void profiler_free(amber_plan_s* p) {
+    Profiler* f = p->prof;
+    if (!f) return;
+    for (int i = 0; i < 2 * f->capacity; ++i)
+        if (f->ev[i]) (void)hipEventDestroy(f->ev[i]);
+    delete[] f->ev;
+    delete[] f->names;
+    delete f;
+    p->prof = nullptr;
+}
+
 void amber_plan_destroy(amber_plan plan) {
     if (!plan) return;
+    profiler_free(plan);
     if (plan->d_tw) (void)hipFree(plan->d_tw);
     delete plan;
+}
+
+int amber_profile_begin(amber_plan plan, int capacity) {
+    if (!plan || capacity < 1 || capacity > (1 << 20)) return AMBER_E_ARG;
+    profiler_free(plan);
+    Profiler* f = new (std::nothrow) Profiler();
+    if (!f) return AMBER_E_ARG;
+    f->ev = new (std::nothrow) hipEvent_t[2 * (size_t)capacity]();
+    f->names = new (std::nothrow) const char*[(size_t)capacity]();
+    plan->prof = f;
+    if (!f->ev || !f->names) {
+        profiler_free(plan);
+        return AMBER_E_ARG;
+    }
+    f->capacity = capacity;
+    for (int i = 0; i < 2 * capacity; ++i) {
+        if (hipEventCreate(&f->ev[i]) != hipSuccess) {
+            f->capacity = i / 2;
+            profiler_free(plan);
+            return AMBER_E_HIP;
+        }
+    }
+    return AMBER_OK;
+}
+
+int amber_profile_end(amber_plan plan, amber_kernel_time* out, int max_entries, int* n_entries) {
+    if (!plan || !plan->prof || (!out && max_entries > 0) || !n_entries) return AMBER_E_ARG;
+    Profiler* f = plan->prof;
+    int n = 0;
+    int rc = AMBER_OK;
+    for (int slot = 0; slot < f->used; ++slot) {
+        if (hipEventSynchronize(f->ev[2 * slot + 1]) != hipSuccess) {
+            rc = AMBER_E_HIP;
+            break;
+        }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, f->ev[2 * slot], f->ev[2 * slot + 1]) != hipSuccess) {
+            rc = AMBER_E_HIP;
+            break;
+        }
+        int k = 0;
+        while (k < n && std::strncmp(out[k].name, f->names[slot], sizeof(out[k].name)) != 0) ++k;
+        if (k == n) {
+            if (n >= max_entries) continue;
+            std::memset(&out[n], 0, sizeof(out[n]));
+            std::strncpy(out[n].name, f->names[slot], sizeof(out[n].name) - 1);
+            ++n;
+        }
+        out[k].launches += 1;
+        out[k].total_ms += (double)ms;
+    }
+    *n_entries = n;
+    profiler_free(plan);
+    return rc;
 }
 
 size_t amber_workspace_bytes(amber_plan plan, int n_lmfp) {

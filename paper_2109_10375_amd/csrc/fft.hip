@@ -394,9 +394,9 @@ int run_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp
     const unsigned g_main = (unsigned)N * (H / C), g_nyq = (unsigned)(N / C);
     const MulArgs none{0.f, 0.f, 0.f, 0};
 
-    hipLaunchKernelGGL((k_fft_z_r2c<N>), dim3(zgrid), zblk, 0, s, d_src, spec_a, nyq_a, tw, n_lines);
-    hipLaunchKernelGGL((k_fft_cols<N, 0, false>), dim3(g_main), cblk, 0, s, spec_a, spec_a, tw, y_main, none);
-    hipLaunchKernelGGL((k_fft_cols<N, 0, false>), dim3(g_nyq), cblk, 0, s, nyq_a, nyq_a, tw, y_nyq, none);
+    AMBER_LAUNCH(p, "fft_z_r2c", (k_fft_z_r2c<N>), dim3(zgrid), zblk, s, d_src, spec_a, nyq_a, tw, n_lines);
+    AMBER_LAUNCH(p, "fft_y", (k_fft_cols<N, 0, false>), dim3(g_main), cblk, s, spec_a, spec_a, tw, y_main, none);
+    AMBER_LAUNCH(p, "fft_nyq_y", (k_fft_cols<N, 0, false>), dim3(g_nyq), cblk, s, nyq_a, nyq_a, tw, y_nyq, none);
     for (int i = 0; i < n_lmfp; ++i) {
         float2* so = (n_lmfp == 1) ? spec_a : spec_b;
         float2* no = (n_lmfp == 1) ? nyq_a : nyq_b;
@@ -404,11 +404,11 @@ int run_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp
         const float sc = (float)(1.0 / ((double)N * N * N));
         const MulArgs mm{k0, (float)l_mfp[i], sc, 0};
         const MulArgs mn{k0, (float)l_mfp[i], sc, 1};
-        hipLaunchKernelGGL((k_fft_cols<N, 1, false>), dim3(g_main), cblk, 0, s, spec_a, so, tw, x_main, mm);
-        hipLaunchKernelGGL((k_fft_cols<N, 1, false>), dim3(g_nyq), cblk, 0, s, nyq_a, no, tw, x_nyq, mn);
-        hipLaunchKernelGGL((k_fft_cols<N, 0, true>), dim3(g_main), cblk, 0, s, so, so, tw, y_main, none);
-        hipLaunchKernelGGL((k_fft_cols<N, 0, true>), dim3(g_nyq), cblk, 0, s, no, no, tw, y_nyq, none);
-        hipLaunchKernelGGL((k_fft_z_c2r<N>), dim3(zgrid), zblk, 0, s, so, no, d_J[i], tw, n_lines);
+        AMBER_LAUNCH(p, "fft_x_mul", (k_fft_cols<N, 1, false>), dim3(g_main), cblk, s, spec_a, so, tw, x_main, mm);
+        AMBER_LAUNCH(p, "fft_nyq_x_mul", (k_fft_cols<N, 1, false>), dim3(g_nyq), cblk, s, nyq_a, no, tw, x_nyq, mn);
+        AMBER_LAUNCH(p, "fft_y_inv", (k_fft_cols<N, 0, true>), dim3(g_main), cblk, s, so, so, tw, y_main, none);
+        AMBER_LAUNCH(p, "fft_nyq_y_inv", (k_fft_cols<N, 0, true>), dim3(g_nyq), cblk, s, no, no, tw, y_nyq, none);
+        AMBER_LAUNCH(p, "fft_z_c2r", (k_fft_z_c2r<N>), dim3(zgrid), zblk, s, so, no, d_J[i], tw, n_lines);
     }
     AMBER_HIP_CHECK(hipGetLastError());
     return AMBER_OK;

@@ -8,12 +8,48 @@
 
 #include "../../include/amber.h"
 
+// Optional per-kernel timing: a pool of HIP event pairs recorded around each
+// launch on the launch's own stream (amber_profile_begin / amber_profile_end).
+struct Profiler {
+    int capacity = 0;
+    int used = 0;
+    int dropped = 0;
+    hipEvent_t* ev = nullptr;     // 2 * capacity events
+    const char** names = nullptr;  // kernel name per slot
+};
+
 struct amber_plan_s {
     int n = 0;             // grid size per axis
     double box_len = 0.0;  // box side
     int device = -1;
     float2* d_tw = nullptr;  // tw[j] = exp(-2 pi i j / n), j < n, FP64-rounded to FP32
+    Profiler* prof = nullptr;
 };
+
+inline int prof_start(const amber_plan_s* p, const char* name, hipStream_t s) {
+    Profiler* f = p->prof;
+    if (!f) return -1;
+    if (f->used >= f->capacity) {
+        ++f->dropped;
+        return -1;
+    }
+    const int slot = f->used++;
+    f->names[slot] = name;
+    (void)hipEventRecord(f->ev[2 * slot], s);
+    return slot;
+}
+
+inline void prof_stop(const amber_plan_s* p, int slot, hipStream_t s) {
+    if (slot >= 0) (void)hipEventRecord(p->prof->ev[2 * slot + 1], s);
+}
+
+// Launch with optional timing.  KERNEL may be a parenthesised template-id.
+#define AMBER_LAUNCH(plan, name, KERNEL, grid, block, stream, ...)                  \
+    do {                                                                          \
+        const int slot_ = prof_start((plan), (name), (stream));                   \
+        hipLaunchKernelGGL(KERNEL, grid, block, 0, stream, __VA_ARGS__);          \
+        prof_stop((plan), slot_, (stream));                                       \
+    } while (0)
 
 // Byte layout of the caller's workspace for one plan.
 struct WsLayout {

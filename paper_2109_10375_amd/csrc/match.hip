@@ -260,8 +260,8 @@ int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, flo
             const amber_weibull& w = hist[h0 + i];
             hs.h[i] = HistArg{w.a_w, w.h, w.z_top, (long long)(w.table_n - 1), w.d_table, d_zre[h0 + i]};
         }
-        hipLaunchKernelGGL(k_scan_invert, dim3((unsigned)n_tiles), dim3(kThreads), 0, s, perm, w_sorted, n, ctrl, lb,
-                           hs);
+        AMBER_LAUNCH(p, "match_scan_invert", k_scan_invert, dim3((unsigned)n_tiles), dim3(kThreads), s, perm, w_sorted,
+                     n, ctrl, lb, hs);
     }
     AMBER_HIP_CHECK(hipGetLastError());
     return AMBER_OK;

@@ -411,33 +411,33 @@ int rank_sort(const amber_plan_s* p, const float* d_J, const float* d_w, unsigne
     unsigned long long* tile_sums =
         reinterpret_cast<unsigned long long*>(ws + L.lookback + (size_t)n_tiles * 256 * 4 * 2);
 
-    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(256), 0, s, ctrl);
+    AMBER_LAUNCH(p, "rank_init", k_ctrl_init, dim3(1), dim3(256), s, ctrl);
     const unsigned hist_blocks = (unsigned)std::min<long long>(2048, (n + kThreads * 16 - 1) / (kThreads * 16));
-    hipLaunchKernelGGL(k_hist, dim3(hist_blocks), dim3(kThreads), 0, s, d_J, n, ctrl, lb[0], n_tiles * 256);
-    hipLaunchKernelGGL(k_digit_offsets, dim3(1), dim3(kThreads), 0, s, ctrl);
+    AMBER_LAUNCH(p, "rank_hist", k_hist, dim3(hist_blocks), dim3(kThreads), s, d_J, n, ctrl, lb[0], n_tiles * 256);
+    AMBER_LAUNCH(p, "rank_digit_offsets", k_digit_offsets, dim3(1), dim3(kThreads), s, ctrl);
     const dim3 grid((unsigned)n_tiles), blk(kThreads);
     // pass 0: J, w -> buffers 1; pass 1: 1 -> 0; pass 2: 0 -> 1; pass 3: 1 -> 0 (values, weights)
     uint32_t* final_vals = d_perm_out ? d_perm_out : vals[0];
     if (carry) {
-        hipLaunchKernelGGL((k_onesweep<true, false, true>), grid, blk, 0, s, d_J, nullptr, nullptr, d_w, keys[1],
+        AMBER_LAUNCH(p, "rank_pass0", (k_onesweep<true, false, true>), grid, blk, s, d_J, nullptr, nullptr, d_w, keys[1],
                            vals[1], wts[1], lb[0], lb[1], nullptr, ctrl, 0, n);
-        hipLaunchKernelGGL((k_onesweep<false, false, true>), grid, blk, 0, s, nullptr, keys[1], vals[1], wts[1],
+        AMBER_LAUNCH(p, "rank_pass1", (k_onesweep<false, false, true>), grid, blk, s, nullptr, keys[1], vals[1], wts[1],
                            keys[0], vals[0], wts[0], lb[1], lb[0], tile_sums, ctrl, 1, n);
-        hipLaunchKernelGGL((k_onesweep<false, false, true>), grid, blk, 0, s, nullptr, keys[0], vals[0], wts[0],
+        AMBER_LAUNCH(p, "rank_pass2", (k_onesweep<false, false, true>), grid, blk, s, nullptr, keys[0], vals[0], wts[0],
                            keys[1], vals[1], wts[1], lb[0], lb[1], nullptr, ctrl, 2, n);
-        hipLaunchKernelGGL((k_onesweep<false, true, true>), grid, blk, 0, s, nullptr, keys[1], vals[1], wts[1],
+        AMBER_LAUNCH(p, "rank_pass3", (k_onesweep<false, true, true>), grid, blk, s, nullptr, keys[1], vals[1], wts[1],
                            nullptr, final_vals, wts[0], lb[1], lb[0], nullptr, ctrl, 3, n);
-        hipLaunchKernelGGL(k_total, dim3(1), dim3(kThreads), 0, s, tile_sums, n_tiles, ctrl);
+        AMBER_LAUNCH(p, "match_total", k_total, dim3(1), dim3(kThreads), s, tile_sums, n_tiles, ctrl);
         const unsigned rb = (unsigned)std::min<long long>(1024, (n + kThreads * 16 - 1) / (kThreads * 16));
-        hipLaunchKernelGGL(k_range, dim3(rb), dim3(kThreads), 0, s, wts[0], n, ctrl);
+        AMBER_LAUNCH(p, "match_range", k_range, dim3(rb), dim3(kThreads), s, wts[0], n, ctrl);
     } else {
-        hipLaunchKernelGGL((k_onesweep<true, false, false>), grid, blk, 0, s, d_J, nullptr, nullptr, nullptr, keys[1],
+        AMBER_LAUNCH(p, "rank_pass0", (k_onesweep<true, false, false>), grid, blk, s, d_J, nullptr, nullptr, nullptr, keys[1],
                            vals[1], nullptr, lb[0], lb[1], nullptr, ctrl, 0, n);
-        hipLaunchKernelGGL((k_onesweep<false, false, false>), grid, blk, 0, s, nullptr, keys[1], vals[1], nullptr,
+        AMBER_LAUNCH(p, "rank_pass1", (k_onesweep<false, false, false>), grid, blk, s, nullptr, keys[1], vals[1], nullptr,
                            keys[0], vals[0], nullptr, lb[1], lb[0], nullptr, ctrl, 1, n);
-        hipLaunchKernelGGL((k_onesweep<false, false, false>), grid, blk, 0, s, nullptr, keys[0], vals[0], nullptr,
+        AMBER_LAUNCH(p, "rank_pass2", (k_onesweep<false, false, false>), grid, blk, s, nullptr, keys[0], vals[0], nullptr,
                            keys[1], vals[1], nullptr, lb[0], lb[1], nullptr, ctrl, 2, n);
-        hipLaunchKernelGGL((k_onesweep<false, true, false>), grid, blk, 0, s, nullptr, keys[1], vals[1], nullptr,
+        AMBER_LAUNCH(p, "rank_pass3", (k_onesweep<false, true, false>), grid, blk, s, nullptr, keys[1], vals[1], nullptr,
                            nullptr, final_vals, nullptr, lb[1], lb[0], nullptr, ctrl, 3, n);
     }
     AMBER_HIP_CHECK(hipGetLastError());
