@@ -58,8 +58,10 @@ def algorithmic_bytes(n: int) -> dict:
         "rank_pass1": 12 * n3 + 12 * n3,
         "rank_pass2": 12 * n3 + 12 * n3,
         "rank_pass3": 12 * n3 + 8 * n3,      # index, w out
-        "match_range": 4 * n3,
-        "match_scan_invert": 8 * n3 + 4 * n3,  # index, w in; z_re out
+        "match_tile_sums": 4 * n3,                 # sorted weights in
+        "match_scan_partition": 8 * n3 + 8 * n3,   # rank order, w in; (cell, z) pairs out
+        "match_partition2": 8 * n3 + 8 * n3,       # (cell, z) pairs in and out
+        "match_leaf_scatter": 8 * n3 + 4 * n3,     # (cell, z) pairs in; z_re out
     }
 
 

@@ -107,8 +107,9 @@ WsLayout ws_layout(int n, int n_lmfp) {
     for (int i = 0; i < 2; ++i) { L.keys[i] = r; r = align256(r + n3 * 4); }
     for (int i = 0; i < 2; ++i) { L.vals[i] = r; r = align256(r + n3 * 4); }
     for (int i = 0; i < 2; ++i) { L.wts[i] = r; r = align256(r + n3 * 4); }
+    for (int i = 0; i < 2; ++i) { L.part2[i] = r; r = align256(r + n3 * 4); }
     L.lookback = r;
-    r = align256(r + n_tiles * 256 * 4 * 2 + n_tiles * 16);
+    r = align256(r + (size_t)lb_words((long long)n3) * 4 * 3 + n_tiles * 16);
     L.total = std::max(f, r);
     return L;
 }

@@ -61,18 +61,23 @@ struct WsLayout {
     size_t keys[2];     // sort keys (ping-pong), N^3 uint32
     size_t vals[2];     // cell indices, N^3 uint32
     size_t wts[2];      // weights carried with the keys, N^3 float
-    size_t lookback;    // decoupled look-back tiles
+    size_t part2[2];    // second-level (cell, z) partition, N^3 uint32 + float
+    size_t lookback;    // decoupled look-back tiles: 3 regions of lb_words() words
     size_t total;
 };
 
 WsLayout ws_layout(int n, int n_lmfp);
+
+// Words in each look-back region: 256 per 4096-cell tile, plus 256 tiles of
+// slack for partitions whose tiles do not straddle buckets.
+inline long long lb_words(long long n3) { return ((n3 + 4095) / 4096 + 256) * 256; }
 
 // Control block (lives at offset 0 of the workspace; zeroed by a kernel at the
 // start of every matching call).
 struct Ctrl {
     unsigned status;            // AMBER_STATUS_* bits (sticky until amber_status)
     unsigned pad0;
-    unsigned tickets[8];        // tile tickets: 0-3 radix passes, 4 scan
+    unsigned tickets[32];       // tile tickets: 0-3 radix passes, 4.. matching launches
     unsigned hist[4][256];      // digit histograms of the descending keys
     unsigned digit_off[4][256]; // exclusive prefix of hist
     unsigned long long msum[256];  // per-FP32-exponent sums of significands of w
@@ -80,6 +85,45 @@ struct Ctrl {
     int wide;                   // 1 when the total needs more than 64 bits
     unsigned long long total_lo, total_hi;  // exact sum of w 2^-qmin
 };
+
+// Decoupled look-back over 30-bit counts with a 2-bit flag (aggregate or
+// inclusive prefix), one word per (tile, entry), 256 entries per tile.  The
+// walk reads 8 predecessors per step, which keeps its latency from growing with
+// the number of tiles in flight; it stops at the first prefix, and every tile
+// at or after first_tile publishes its aggregate before walking, so it ends.
+constexpr unsigned kLbAgg = 1u << 30, kLbPre = 2u << 30, kLbMask = (1u << 30) - 1;
+constexpr int kLbBatch = 8;
+
+__device__ __forceinline__ unsigned lb_walk(const unsigned* lb, long long tile, int d, long long first_tile) {
+    unsigned excl = 0;
+    long long t = tile - 1;
+    while (true) {
+        unsigned v[kLbBatch];
+#pragma unroll
+        for (int k = 0; k < kLbBatch; ++k)
+            v[k] = (t - k >= first_tile)
+                       ? __hip_atomic_load(lb + (t - k) * 256 + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                       : kLbPre;
+        int used = 0;
+        bool done = false, stall = false;
+#pragma unroll
+        for (int k = 0; k < kLbBatch; ++k) {
+            if (done || stall) continue;
+            const unsigned f = v[k] & ~kLbMask;
+            if (f == 0u) {
+                stall = true;
+                continue;
+            }
+            excl += v[k] & kLbMask;
+            ++used;
+            if (f == kLbPre) done = true;
+        }
+        if (done) break;
+        t -= used;
+        if (stall) __builtin_amdgcn_s_sleep(1);
+    }
+    return excl;
+}
 
 // FFT launches (fft.hip).
 int fft_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp, int n_lmfp,

@@ -118,24 +118,21 @@ __device__ __forceinline__ int weight_q(unsigned bits) {
 
 // One digit pass.  FIRST: keys come from J and the index is the position.
 // LAST: only the values (and weights) are written.  CARRY: weights travel with
-// the keys; pass 0 also checks them and finds the smallest ulp exponent, pass 1
-// (when SUMW) writes each tile's exact weight sum for the matching total.
+// the keys; pass 0 also checks them and finds the smallest ulp exponent.
 template <bool FIRST, bool LAST, bool CARRY>
 __global__ __launch_bounds__(kThreads) void k_onesweep(
     const float* __restrict__ J, const unsigned* __restrict__ keys_in, const unsigned* __restrict__ vals_in,
     const float* __restrict__ w_in, unsigned* __restrict__ keys_out, unsigned* __restrict__ vals_out,
     float* __restrict__ w_out, unsigned* __restrict__ lb, unsigned* __restrict__ lb_next,
-    unsigned long long* __restrict__ tile_sums, Ctrl* ctrl, int pass, long long n) {
+    unsigned* __restrict__ lb_next2, Ctrl* ctrl, int pass, long long n) {
     __shared__ unsigned s_tile;
     __shared__ unsigned wcnt[kWaves][256];
     __shared__ unsigned loff[256];
     __shared__ unsigned gbase[256];
     __shared__ unsigned scan_sh[kWaves];
-    __shared__ unsigned st_key[kTile];
-    __shared__ unsigned st_val[kTile];
-    __shared__ float st_w[CARRY ? kTile : 1];
+    __shared__ unsigned stage[kTile];          // keys, then indices, then weights
+    __shared__ unsigned char st_dig[kTile];    // digit of each staged slot
     __shared__ int s_qmin[kWaves];
-    __shared__ unsigned long long s_sum[kWaves][2];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0) s_tile = atomicAdd(&ctrl->tickets[pass], 1u);
@@ -147,6 +144,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
 
     // The next pass's look-back entry for this tile starts cleared.
     if (lb_next) lb_next[(long long)tile * 256 + tid] = 0u;
+    if (lb_next2) lb_next2[(long long)tile * 256 + tid] = 0u;
 
     unsigned key[kKeysPerThread], val[kKeysPerThread], lrank[kKeysPerThread];
     float wt[kKeysPerThread];
@@ -211,19 +209,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
             gbase[d] = ctrl->digit_off[pass][d];
         } else {
             st_release(me, kFlagAgg | tcnt);
-            unsigned excl = 0;
-            long long t = (long long)tile - 1;
-            while (true) {
-                const unsigned v = ld_acquire(lb + t * 256 + d);
-                const unsigned f = v & ~kValMask;
-                if (f == 0u) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                excl += v & kValMask;
-                if (f == kFlagPre) break;
-                --t;
-            }
+            const unsigned excl = lb_walk(lb, (long long)tile, d, 0);
             st_release(me, kFlagPre | (excl + tcnt));
             gbase[d] = ctrl->digit_off[pass][d] + excl;
         }
@@ -252,148 +238,52 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
         if (q < __hip_atomic_load(&ctrl->qmin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(&ctrl->qmin, q);
     }
 
-    // Stage the tile in digit order in LDS.
+    // Stage the tile in digit order in LDS, one array at a time; consecutive
+    // threads then write consecutive slots of a digit run.
+    unsigned lpos[kKeysPerThread];
 #pragma unroll
     for (int j = 0; j < kKeysPerThread; ++j) {
         const bool ok = (wbase + 64 * j + lane) < n;
-        if (ok) {
-            const unsigned dd = (key[j] >> shift) & 255u;
-            const unsigned p = loff[dd] + wcnt[wave][dd] + lrank[j];
-            if (p >= (unsigned)kTile) continue;  // unreachable for consistent counts
-            st_key[p] = key[j];
-            st_val[p] = val[j];
-            if (CARRY) st_w[p] = wt[j];
+        const unsigned dd = (key[j] >> shift) & 255u;
+        const unsigned p = ok ? loff[dd] + wcnt[wave][dd] + lrank[j] : 0xffffffffu;
+        lpos[j] = p < (unsigned)kTile ? p : 0xffffffffu;  // out of range is unreachable for consistent counts
+        if (lpos[j] != 0xffffffffu) {
+            stage[p] = key[j];
+            st_dig[p] = (unsigned char)dd;
         }
     }
     __syncthreads();
-
-    // Write out: consecutive threads write consecutive slots of a digit run.
     const long long valid_ll = n - tile_base;
     const int valid = valid_ll < kTile ? (int)valid_ll : kTile;
-#pragma unroll 4
-    for (int i = tid; i < valid; i += kThreads) {
-        const unsigned k = st_key[i];
-        const unsigned dd = (k >> shift) & 255u;
-        const long long dst = (long long)gbase[dd] + (i - (int)loff[dd]);
-        if (dst < 0 || dst >= n) continue;  // unreachable for consistent counts
-        if (!LAST) keys_out[dst] = k;
-        vals_out[dst] = st_val[i];
-        if (CARRY) w_out[dst] = st_w[i];
-    }
-
-    // Pass 1 of a matching sort: exact tile sum of the weights, w 2^-qmin
-    // (qmin is final once pass 0 has completed).
-    if (CARRY && tile_sums) {
-        const int qm = ctrl->qmin;
-        unsigned long long lo = 0, hi = 0;
-        bool ovf = false;
-#pragma unroll
-        for (int j = 0; j < kKeysPerThread; ++j) {
-            const bool ok = (wbase + 64 * j + lane) < n;
-            if (!ok) continue;
-            const unsigned b = __float_as_uint(wt[j]);
-            const unsigned long long m = (unsigned long long)((b & 0x7fffffu) | ((b >> 23) & 255u ? 0x800000u : 0u));
-            const int sh = weight_q(b) - qm;  // >= 0 for valid weights
-            unsigned long long tlo, thi;
-            if (sh >= 128 || sh < 0) {
-                tlo = 0; thi = 0;  // out of range: reported by k_range
-            } else if (sh >= 64) {
-                tlo = 0; thi = m << (sh - 64);
-            } else if (sh == 0) {
-                tlo = m; thi = 0;
-            } else {
-                tlo = m << sh; thi = m >> (64 - sh);
-            }
-            const unsigned long long nlo = lo + tlo;
-            const unsigned long long nhi = hi + thi + (nlo < lo ? 1ull : 0ull);
-            ovf |= nhi < hi;
-            lo = nlo;
-            hi = nhi;
-        }
-        // wave reduce (128-bit)
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const unsigned long long olo = __shfl_xor(lo, o, 64);
-            const unsigned long long ohi = __shfl_xor(hi, o, 64);
-            const unsigned long long nlo = lo + olo;
-            const unsigned long long nhi = hi + ohi + (nlo < lo ? 1ull : 0ull);
-            ovf |= nhi < hi;
-            lo = nlo;
-            hi = nhi;
-        }
-        if (__any(ovf) && lane == 0) atomicOr(&ctrl->status, AMBER_STATUS_RANGE);
-        if (lane == 0) {
-            s_sum[wave][0] = lo;
-            s_sum[wave][1] = hi;
+    if (!LAST) {
+        for (int i = tid; i < valid; i += kThreads) {
+            const unsigned dd = st_dig[i];
+            const long long dst = (long long)gbase[dd] + (i - (int)loff[dd]);
+            if (dst >= 0 && dst < n) keys_out[dst] = stage[i];
         }
         __syncthreads();
-        if (tid == 0) {
-            unsigned long long a = 0, b = 0;
-            bool ov = false;
-            for (int w = 0; w < kWaves; ++w) {
-                const unsigned long long nlo = a + s_sum[w][0];
-                const unsigned long long nb = b + s_sum[w][1] + (nlo < a ? 1ull : 0ull);
-                ov |= nb < b;
-                a = nlo;
-                b = nb;
-            }
-            if (ov) atomicOr(&ctrl->status, AMBER_STATUS_RANGE);
-            tile_sums[2 * (long long)tile] = a;
-            tile_sums[2 * (long long)tile + 1] = b;
+    }
+#pragma unroll
+    for (int j = 0; j < kKeysPerThread; ++j)
+        if (lpos[j] != 0xffffffffu) stage[lpos[j]] = val[j];
+    __syncthreads();
+    for (int i = tid; i < valid; i += kThreads) {
+        const unsigned dd = st_dig[i];
+        const long long dst = (long long)gbase[dd] + (i - (int)loff[dd]);
+        if (dst >= 0 && dst < n) vals_out[dst] = stage[i];
+    }
+    if (CARRY) {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kKeysPerThread; ++j)
+            if (lpos[j] != 0xffffffffu) stage[lpos[j]] = __float_as_uint(wt[j]);
+        __syncthreads();
+        for (int i = tid; i < valid; i += kThreads) {
+            const unsigned dd = st_dig[i];
+            const long long dst = (long long)gbase[dd] + (i - (int)loff[dd]);
+            if (dst >= 0 && dst < n) w_out[dst] = __uint_as_float(stage[i]);
         }
     }
-}
-
-// Sum of the tile sums -> exact total (must stay below 2^127) and width flag.
-__global__ __launch_bounds__(kThreads) void k_total(const unsigned long long* __restrict__ tile_sums, long long n_tiles,
-                                                    Ctrl* ctrl) {
-    __shared__ unsigned long long s[kThreads][2];
-    __shared__ int s_bad;
-    if (threadIdx.x == 0) s_bad = 0;
-    __syncthreads();
-    unsigned long long lo = 0, hi = 0;
-    bool bad = false;
-    for (long long t = threadIdx.x; t < n_tiles; t += kThreads) {
-        const unsigned long long a = tile_sums[2 * t], b = tile_sums[2 * t + 1];
-        const unsigned long long nlo = lo + a;
-        const unsigned long long nhi = hi + b + (nlo < lo ? 1ull : 0ull);
-        bad |= nhi < hi;
-        lo = nlo;
-        hi = nhi;
-    }
-    s[threadIdx.x][0] = lo;
-    s[threadIdx.x][1] = hi;
-    if (bad) s_bad = 1;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long a = 0, b = 0;
-        bool ov = s_bad != 0;
-        for (int i = 0; i < kThreads; ++i) {
-            const unsigned long long nlo = a + s[i][0];
-            const unsigned long long nb = b + s[i][1] + (nlo < a ? 1ull : 0ull);
-            ov |= nb < b;
-            a = nlo;
-            b = nb;
-        }
-        ov |= (b >> 63) != 0ull;
-        ctrl->total_lo = a;
-        ctrl->total_hi = b;
-        ctrl->wide = (b != 0ull);
-        if (ov) atomicOr(&ctrl->status, AMBER_STATUS_RANGE);
-    }
-}
-
-// Flags weights whose scaled value m 2^(q - qmin) would need 128 bits or more.
-__global__ __launch_bounds__(kThreads) void k_range(const float* __restrict__ w, long long n, Ctrl* ctrl) {
-    const int qm = ctrl->qmin;
-    bool bad = false;
-    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
-        const unsigned b = __float_as_uint(w[i]);
-        const unsigned m = (b & 0x7fffffu) | (((b >> 23) & 255u) ? 0x800000u : 0u);
-        const int bits = m ? 32 - __clz(m) : 0;
-        bad |= (weight_q(b) - qm) + bits > 127;
-    }
-    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&ctrl->status, AMBER_STATUS_RANGE);
 }
 
 }  // namespace
@@ -406,10 +296,10 @@ int rank_sort(const amber_plan_s* p, const float* d_J, const float* d_w, unsigne
     unsigned* keys[2] = {reinterpret_cast<unsigned*>(ws + L.keys[0]), reinterpret_cast<unsigned*>(ws + L.keys[1])};
     unsigned* vals[2] = {reinterpret_cast<unsigned*>(ws + L.vals[0]), reinterpret_cast<unsigned*>(ws + L.vals[1])};
     float* wts[2] = {reinterpret_cast<float*>(ws + L.wts[0]), reinterpret_cast<float*>(ws + L.wts[1])};
-    unsigned* lb[2] = {reinterpret_cast<unsigned*>(ws + L.lookback),
-                       reinterpret_cast<unsigned*>(ws + L.lookback) + n_tiles * 256};
-    unsigned long long* tile_sums =
-        reinterpret_cast<unsigned long long*>(ws + L.lookback + (size_t)n_tiles * 256 * 4 * 2);
+    const long long lbw = lb_words(n);
+    unsigned* lb[3] = {reinterpret_cast<unsigned*>(ws + L.lookback),
+                       reinterpret_cast<unsigned*>(ws + L.lookback) + lbw,
+                       reinterpret_cast<unsigned*>(ws + L.lookback) + 2 * lbw};
 
     AMBER_LAUNCH(p, "rank_init", k_ctrl_init, dim3(1), dim3(256), s, ctrl);
     const unsigned hist_blocks = (unsigned)std::min<long long>(2048, (n + kThreads * 16 - 1) / (kThreads * 16));
@@ -422,14 +312,11 @@ int rank_sort(const amber_plan_s* p, const float* d_J, const float* d_w, unsigne
         AMBER_LAUNCH(p, "rank_pass0", (k_onesweep<true, false, true>), grid, blk, s, d_J, nullptr, nullptr, d_w, keys[1],
                            vals[1], wts[1], lb[0], lb[1], nullptr, ctrl, 0, n);
         AMBER_LAUNCH(p, "rank_pass1", (k_onesweep<false, false, true>), grid, blk, s, nullptr, keys[1], vals[1], wts[1],
-                           keys[0], vals[0], wts[0], lb[1], lb[0], tile_sums, ctrl, 1, n);
+                           keys[0], vals[0], wts[0], lb[1], lb[0], nullptr, ctrl, 1, n);
         AMBER_LAUNCH(p, "rank_pass2", (k_onesweep<false, false, true>), grid, blk, s, nullptr, keys[0], vals[0], wts[0],
                            keys[1], vals[1], wts[1], lb[0], lb[1], nullptr, ctrl, 2, n);
         AMBER_LAUNCH(p, "rank_pass3", (k_onesweep<false, true, true>), grid, blk, s, nullptr, keys[1], vals[1], wts[1],
-                           nullptr, final_vals, wts[0], lb[1], lb[0], nullptr, ctrl, 3, n);
-        AMBER_LAUNCH(p, "match_total", k_total, dim3(1), dim3(kThreads), s, tile_sums, n_tiles, ctrl);
-        const unsigned rb = (unsigned)std::min<long long>(1024, (n + kThreads * 16 - 1) / (kThreads * 16));
-        AMBER_LAUNCH(p, "match_range", k_range, dim3(rb), dim3(kThreads), s, wts[0], n, ctrl);
+                           nullptr, final_vals, wts[0], lb[1], lb[0], lb[2], ctrl, 3, n);
     } else {
         AMBER_LAUNCH(p, "rank_pass0", (k_onesweep<true, false, false>), grid, blk, s, d_J, nullptr, nullptr, nullptr, keys[1],
                            vals[1], nullptr, lb[0], lb[1], nullptr, ctrl, 0, n);
@@ -438,7 +325,7 @@ int rank_sort(const amber_plan_s* p, const float* d_J, const float* d_w, unsigne
         AMBER_LAUNCH(p, "rank_pass2", (k_onesweep<false, false, false>), grid, blk, s, nullptr, keys[0], vals[0], nullptr,
                            keys[1], vals[1], nullptr, lb[0], lb[1], nullptr, ctrl, 2, n);
         AMBER_LAUNCH(p, "rank_pass3", (k_onesweep<false, true, false>), grid, blk, s, nullptr, keys[1], vals[1], nullptr,
-                           nullptr, final_vals, nullptr, lb[1], lb[0], nullptr, ctrl, 3, n);
+                           nullptr, final_vals, nullptr, lb[1], lb[0], lb[2], ctrl, 3, n);
     }
     AMBER_HIP_CHECK(hipGetLastError());
     return AMBER_OK;

@@ -36,7 +36,7 @@ def _gpu_hist(amber, H):
 
 # --------------------------------------------------------------- ranking ----
 
-@pytest.mark.parametrize("n,seed", [(8, 1), (16, 2), (32, 3), (64, 4), (96, 5)])
+@pytest.mark.parametrize("n,seed", [(8, 1), (16, 2), (32, 3), (64, 4), (96, 5), (192, 6), (256, 7)])
 def test_rank_bitexact_ties_zeros_negatives(amber, n, seed):
     print(f"rank n={n} seed={seed}", flush=True)
     J = inputs.make_intensity(n, seed)
@@ -83,7 +83,8 @@ def test_rank_nan_sets_status(amber):
 
 # -------------------------------------------------------------- matching ----
 
-@pytest.mark.parametrize("n,seed", [(8, 11), (16, 12), (32, 13), (64, 14), (96, 15)])
+@pytest.mark.parametrize("n,seed", [(8, 11), (16, 12), (32, 13), (64, 14), (96, 15), (128, 16), (192, 17),
+                                    (256, 18)])
 def test_zre_bitexact_same_intensity(amber, n, seed):
     """Given identical J, w and history, GPU z_re equals the oracle's contract
     mode bit for bit."""
@@ -126,6 +127,27 @@ def test_zre_several_histories_share_one_ranking(amber):
     for z, H in zip(zs, Hs):
         z_ref, _ = oracle.zre(J.numpy(), w.numpy(), H, mode=oracle.CONTRACT)
         assert np.array_equal(z.cpu().numpy(), z_ref)
+
+
+def test_zre_more_histories_than_one_launch(amber):
+    """Eight histories (the maximum) run in three launch groups; each result
+    equals the oracle's and equals the same history run alone."""
+    n = 16
+    J = inputs.make_intensity(n, 33)
+    w = inputs.make_density(n, 34).to(torch.float32)
+    hs = [(8.0, 4.0, 3.0), (7.95, 4.68, 2.90), (7.91, 5.45, 2.69), (7.83, 6.54, 2.33),
+          (6.0, 2.0, 1.5), (10.0, 6.0, 4.0), (9.0, 3.0, 1.0), (7.0, 5.0, 2.0)]
+    Hs = [_oracle_hist(h) for h in hs]
+    plan = amber.Plan(n, 1.0)
+    G = [_gpu_hist(amber, H) for H in Hs]
+    zs = plan.zre(J.cuda(), w.cuda(), G)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    for k, (z, H) in enumerate(zip(zs, Hs)):
+        z_ref, _ = oracle.zre(J.numpy(), w.numpy(), H, mode=oracle.CONTRACT)
+        assert np.array_equal(z.cpu().numpy(), z_ref), k
+        (z1,) = plan.zre(J.cuda(), w.cuda(), [G[k]])
+        assert torch.equal(z1, z)
 
 
 def test_zre_bad_weights_set_status(amber):
