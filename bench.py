@@ -65,6 +65,55 @@ def algorithmic_bytes(n: int) -> dict:
     }
 
 
+KERNEL_SOURCES = {"fft_": "fft.hip", "rank_": "rank.hip", "match_": "match.hip"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_box1024.txt")
+
+
+def kernel_source_digest(name: str) -> str | None:
+    """sha256 of the sources a library kernel is compiled from (its .hip file,
+    the shared header and the build flags)."""
+    import hashlib
+
+    src = next((f for pre, f in KERNEL_SOURCES.items() if name.startswith(pre)), None)
+    if src is None:
+        return None
+    pkg = os.path.join(ROOT, "paper_2109_10375_amd")
+    h = hashlib.sha256()
+    for f in (os.path.join(pkg, "csrc", src), os.path.join(pkg, "csrc", "internal.h"), os.path.join(pkg, "build.py")):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(name: str, n: int) -> tuple[float | None, str]:
+    """HBM bytes per launch of `name` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel factor),
+    or None when there is no entry or the kernel's sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None, "no counter summary"
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) >= 10 and f[0] == "kernel" and f[1] == name and int(f[3]) == n:
+                if f[9] != kernel_source_digest(name):
+                    return None, "kernel sources changed since the counters were taken"
+                return float(f[5]) + float(f[7]), "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated"
+    return None, "no counter entry for this kernel"
+
+
+def copy_calibration(mib: int) -> None:
+    """A plain elementwise copy (negation) of `mib` MiB, three times: the known
+    byte count against which the HBM counters are calibrated."""
+    import torch
+
+    src = torch.ones(mib * 2 ** 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: {mib} MiB read + {mib} MiB written per launch, 3 launches")
+
+
 def cpu_baseline(sample_n: int, min_seconds: float) -> dict:
     import numpy as np
 
@@ -104,6 +153,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=128)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain copy of MIB MiB (for HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -148,6 +199,9 @@ def main() -> int:
     if st:
         raise RuntimeError(f"device status {st} after warmup")
 
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     plan.profile_begin(64 * args.steps)
@@ -182,8 +236,9 @@ def main() -> int:
         log(f"[bench] {name:22s} {launches:8d} {avg:9.3f} {100 * tot_ms / tot_all:5.1f}% "
             f"{(b or 0) / 1e9:8.2f} {gbs or 0:8.0f} {100 * (gbs or 0) / HBM_PEAK_GBS:5.1f}")
     dom = next(r for r in rows if r[4])
+    traffic, traffic_src = measured_traffic(dom[1], n)
     roof = {"bound": "hbm", "kernel": dom[1], "achieved": round(dom[5], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(dom[5] / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(dom[5] / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": traffic_src,
             "algorithmic_bytes_per_launch": dom[4], "avg_launch_ms": round(dom[3], 4)}
     pipe_bytes = sum(alg[r[1]] * r[2] for r in rows if r[1] in alg) / args.steps
     out = {
