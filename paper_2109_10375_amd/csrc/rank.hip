@@ -6,7 +6,8 @@
 // of the intensity (-0 folded onto +0).  The input is read in cell-index order
 // and every pass is stable, so equal intensities keep ascending cell index.
 //
-// Each pass ("onesweep"): a block takes the next 4096-key tile from a ticket
+// Each pass ("onesweep"): a block takes the next tile (16384 keys; long digit
+// runs keep the scattered writes close to whole cache lines) from a ticket
 // counter, ranks its keys by digit with 64-lane ballots (the lanes that share a
 // digit find each other with 8 ballots; the lowest of them bumps the wave's LDS
 // counter), publishes its per-digit counts for later tiles and looks back over
@@ -20,13 +21,18 @@
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kHistThreads = 256;
+constexpr int kHistWaves = kHistThreads / 64;
+#ifndef AMBER_SORT_THREADS
+#define AMBER_SORT_THREADS 1024
+#endif
+constexpr int kThreads = AMBER_SORT_THREADS;  // one onesweep tile per block
 constexpr int kWaves = kThreads / 64;
 constexpr int kKeysPerThread = 16;
-constexpr int kTile = kThreads * kKeysPerThread;  // 4096
+constexpr int kTile = kThreads * kKeysPerThread;
+static_assert(kThreads >= 256 && kThreads % 64 == 0 && kTile <= 65535, "tile geometry");
 constexpr unsigned kFlagAgg = 1u << 30;
 constexpr unsigned kFlagPre = 2u << 30;
-constexpr unsigned kValMask = (1u << 30) - 1;
 
 __device__ __forceinline__ unsigned desc_key(float f) {
     unsigned u = __float_as_uint(f);
@@ -37,57 +43,75 @@ __device__ __forceinline__ unsigned desc_key(float f) {
 
 __device__ __forceinline__ bool is_nan_bits(unsigned u) { return (u & 0x7fffffffu) > 0x7f800000u; }
 
-__device__ __forceinline__ unsigned ld_acquire(const unsigned* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ void st_release(unsigned* p, unsigned v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Inclusive block-wide scan of one unsigned per thread (256 threads).
-__device__ __forceinline__ unsigned block_incl_scan(unsigned v, unsigned* sh /* kWaves */) {
+// Exclusive scan over 256 values held by threads 0..255 (waves 0-3); every
+// thread of the block calls it (it contains a barrier), the result is defined
+// for threads 0..255.
+__device__ __forceinline__ unsigned digit_excl_scan(unsigned v, unsigned* sh /* 4 */) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned x = v;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-        unsigned o = __shfl_up(v, d, 64);
-        if (lane >= d) v += o;
+        const unsigned o = __shfl_up(x, d, 64);
+        if (lane >= d) x += o;
     }
-    if (lane == 63) sh[wave] = v;
+    if (wave < 4 && lane == 63) sh[wave] = x;
     __syncthreads();
     unsigned add = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w)
+    for (int w = 0; w < 4; ++w)
         if (w < wave) add += sh[w];
-    __syncthreads();
-    return v + add;
+    return x + add - v;
 }
 
-// Clears the control block and the first look-back buffer, counts the four
-// digit histograms of the keys (read once), and flags NaN intensities.
-__global__ __launch_bounds__(kThreads) void k_hist(const float* __restrict__ J, long long n, Ctrl* ctrl,
-                                                   unsigned* __restrict__ lb0, long long lb_words) {
-    __shared__ unsigned h[kWaves][4][256];
+// Clears the control block's histograms' look-back companion region, counts
+// the four digit histograms of the keys (read once, 16 per thread in flight),
+// and flags NaN intensities.  n is a multiple of 4.
+__global__ __launch_bounds__(kHistThreads) void k_hist(const float* __restrict__ J, long long n, Ctrl* ctrl,
+                                                       unsigned* __restrict__ lb0, long long lb_words) {
+    __shared__ unsigned h[kHistWaves][4][256];
     const int wave = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < kWaves * 4 * 256; i += kThreads) (&h[0][0][0])[i] = 0;
-    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < lb_words; i += (long long)gridDim.x * kThreads)
+    for (int i = threadIdx.x; i < kHistWaves * 4 * 256; i += kHistThreads) (&h[0][0][0])[i] = 0;
+    for (long long i = (long long)blockIdx.x * kHistThreads + threadIdx.x; i < lb_words;
+         i += (long long)gridDim.x * kHistThreads)
         lb0[i] = 0;
     __syncthreads();
     bool nan = false;
-    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
-        const float f = J[i];
-        nan |= is_nan_bits(__float_as_uint(f));
-        const unsigned k = desc_key(f);
-        atomicAdd(&h[wave][0][k & 255u], 1u);
-        atomicAdd(&h[wave][1][(k >> 8) & 255u], 1u);
-        atomicAdd(&h[wave][2][(k >> 16) & 255u], 1u);
-        atomicAdd(&h[wave][3][k >> 24], 1u);
+    const float4* J4 = reinterpret_cast<const float4*>(J);
+    const long long n4 = n / 4;
+    constexpr int kV = 4;  // float4 loads per thread per round
+    for (long long base = (long long)blockIdx.x * kHistThreads * kV; base < n4;
+         base += (long long)gridDim.x * kHistThreads * kV) {
+        float4 v[kV];
+#pragma unroll
+        for (int k = 0; k < kV; ++k) {
+            const long long i = base + k * kHistThreads + threadIdx.x;
+            v[k] = i < n4 ? J4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int k = 0; k < kV; ++k) {
+            if (base + k * kHistThreads + threadIdx.x >= n4) continue;
+            const float f[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                nan |= is_nan_bits(__float_as_uint(f[e]));
+                const unsigned key = desc_key(f[e]);
+                atomicAdd(&h[wave][0][key & 255u], 1u);
+                atomicAdd(&h[wave][1][(key >> 8) & 255u], 1u);
+                atomicAdd(&h[wave][2][(key >> 16) & 255u], 1u);
+                atomicAdd(&h[wave][3][key >> 24], 1u);
+            }
+        }
     }
     if (__any(nan) && (threadIdx.x & 63) == 0) atomicOr(&ctrl->status, AMBER_STATUS_NAN_J);
     __syncthreads();
-    for (int i = threadIdx.x; i < 4 * 256; i += kThreads) {
+    for (int i = threadIdx.x; i < 4 * 256; i += kHistThreads) {
         unsigned s = 0;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) s += (&h[w][0][0])[i];
+        for (int w = 0; w < kHistWaves; ++w) s += (&h[w][0][0])[i];
         if (s) atomicAdd(&ctrl->hist[0][0] + i, s);
     }
 }
@@ -100,12 +124,13 @@ __global__ void k_ctrl_init(Ctrl* ctrl) {
 }
 
 // Exclusive prefix of each digit histogram: where each digit's run starts.
-__global__ __launch_bounds__(kThreads) void k_digit_offsets(Ctrl* ctrl) {
-    __shared__ unsigned sh[kWaves];
+__global__ __launch_bounds__(256) void k_digit_offsets(Ctrl* ctrl) {
+    __shared__ unsigned sh[4];
     for (int d = 0; d < 4; ++d) {
         const unsigned v = ctrl->hist[d][threadIdx.x];
-        const unsigned inc = block_incl_scan(v, sh);
-        ctrl->digit_off[d][threadIdx.x] = inc - v;
+        const unsigned ex = digit_excl_scan(v, sh);
+        ctrl->digit_off[d][threadIdx.x] = ex;
+        __syncthreads();
     }
 }
 
@@ -116,9 +141,10 @@ __device__ __forceinline__ int weight_q(unsigned bits) {
     return (e == 0 ? 1 : e) - 150;
 }
 
-// One digit pass.  FIRST: keys come from J and the index is the position.
-// LAST: only the values (and weights) are written.  CARRY: weights travel with
-// the keys; pass 0 also checks them and finds the smallest ulp exponent.
+// One digit pass over tiles of kTile keys.  FIRST: keys come from J and the
+// index is the position.  LAST: only the values (and weights) are written.
+// CARRY: weights travel with the keys; pass 0 also checks them and finds the
+// smallest ulp exponent.
 template <bool FIRST, bool LAST, bool CARRY>
 __global__ __launch_bounds__(kThreads) void k_onesweep(
     const float* __restrict__ J, const unsigned* __restrict__ keys_in, const unsigned* __restrict__ vals_in,
@@ -126,25 +152,26 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     float* __restrict__ w_out, unsigned* __restrict__ lb, unsigned* __restrict__ lb_next,
     unsigned* __restrict__ lb_next2, Ctrl* ctrl, int pass, long long n) {
     __shared__ unsigned s_tile;
-    __shared__ unsigned wcnt[kWaves][256];
-    __shared__ unsigned loff[256];
-    __shared__ unsigned gbase[256];
-    __shared__ unsigned scan_sh[kWaves];
-    __shared__ unsigned stage[kTile];          // keys, then indices, then weights
-    __shared__ unsigned char st_dig[kTile];    // digit of each staged slot
+    __shared__ unsigned short wcnt[kWaves][256];  // per-wave digit counts, then wave offsets
+    __shared__ unsigned loff[256];                // tile-local start of each digit
+    __shared__ unsigned gbase[256];               // global start of each digit's run of this tile
+    __shared__ unsigned scan_sh[4];
+    __shared__ unsigned stage[kTile];             // keys, then indices, then weights, in digit order
     __shared__ int s_qmin[kWaves];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0) s_tile = atomicAdd(&ctrl->tickets[pass], 1u);
-    for (int i = tid; i < kWaves * 256; i += kThreads) (&wcnt[0][0])[i] = 0u;
+    for (int i = tid; i < kWaves * 256; i += kThreads) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     const unsigned tile = s_tile;
     const long long tile_base = (long long)tile * kTile;
     const int shift = 8 * pass;
 
-    // The next pass's look-back entry for this tile starts cleared.
-    if (lb_next) lb_next[(long long)tile * 256 + tid] = 0u;
-    if (lb_next2) lb_next2[(long long)tile * 256 + tid] = 0u;
+    // The next passes' look-back entries for this tile start cleared.
+    if (tid < 256) {
+        if (lb_next) lb_next[(long long)tile * 256 + tid] = 0u;
+        if (lb_next2) lb_next2[(long long)tile * 256 + tid] = 0u;
+    }
 
     unsigned key[kKeysPerThread], val[kKeysPerThread], lrank[kKeysPerThread];
     float wt[kKeysPerThread];
@@ -192,17 +219,24 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
             const unsigned cnt = (unsigned)__popcll(peers);
             const unsigned old = wcnt[wave][d];
             r = old + before;
-            if (before == 0) wcnt[wave][d] = old + cnt;  // lowest peer updates
+            if (before == 0) wcnt[wave][d] = (unsigned short)(old + cnt);  // lowest peer updates
         }
         lrank[j] = r;
     }
     __syncthreads();
 
-    // Per digit: wave offsets, tile count, look-back, tile-local start.
-    const int d = tid;
-    const unsigned c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
-    const unsigned tcnt = c0 + c1 + c2 + c3;
-    {
+    // Per digit (threads 0..255): wave offsets, tile count, look-back.
+    unsigned tcnt = 0;
+    if (tid < 256) {
+        const int d = tid;
+        unsigned run = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const unsigned c = wcnt[w][d];
+            wcnt[w][d] = (unsigned short)run;
+            run += c;
+        }
+        tcnt = run;
         unsigned* me = lb + (long long)tile * 256 + d;
         if (tile == 0) {
             st_release(me, kFlagPre | tcnt);
@@ -214,12 +248,8 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
             gbase[d] = ctrl->digit_off[pass][d] + excl;
         }
     }
-    const unsigned incl = block_incl_scan(tcnt, scan_sh);
-    loff[d] = incl - tcnt;
-    wcnt[0][d] = 0;
-    wcnt[1][d] = c0;
-    wcnt[2][d] = c0 + c1;
-    wcnt[3][d] = c0 + c1 + c2;
+    const unsigned lo = digit_excl_scan(tcnt, scan_sh);
+    if (tid < 256) loff[tid] = lo;
     // block-level reductions of the weight checks (pass 0)
     if (CARRY && FIRST) {
         int q = qmin;
@@ -238,8 +268,9 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
         if (q < __hip_atomic_load(&ctrl->qmin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(&ctrl->qmin, q);
     }
 
-    // Stage the tile in digit order in LDS, one array at a time; consecutive
-    // threads then write consecutive slots of a digit run.
+    // Stage the keys in digit order; every thread then takes the slots
+    // tid + k kThreads, finds each slot's destination from the staged key's
+    // digit, and keeps it for the indices and weights staged after it.
     unsigned lpos[kKeysPerThread];
 #pragma unroll
     for (int j = 0; j < kKeysPerThread; ++j) {
@@ -247,42 +278,43 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
         const unsigned dd = (key[j] >> shift) & 255u;
         const unsigned p = ok ? loff[dd] + wcnt[wave][dd] + lrank[j] : 0xffffffffu;
         lpos[j] = p < (unsigned)kTile ? p : 0xffffffffu;  // out of range is unreachable for consistent counts
-        if (lpos[j] != 0xffffffffu) {
-            stage[p] = key[j];
-            st_dig[p] = (unsigned char)dd;
-        }
+        if (lpos[j] != 0xffffffffu) stage[p] = key[j];
     }
     __syncthreads();
     const long long valid_ll = n - tile_base;
     const int valid = valid_ll < kTile ? (int)valid_ll : kTile;
-    if (!LAST) {
-        for (int i = tid; i < valid; i += kThreads) {
-            const unsigned dd = st_dig[i];
-            const long long dst = (long long)gbase[dd] + (i - (int)loff[dd]);
-            if (dst >= 0 && dst < n) keys_out[dst] = stage[i];
+    unsigned dst[kKeysPerThread];
+#pragma unroll
+    for (int k = 0; k < kKeysPerThread; ++k) {
+        const int i = tid + k * kThreads;
+        dst[k] = 0xffffffffu;
+        if (i < valid) {
+            const unsigned kk = stage[i];
+            const unsigned dd = (kk >> shift) & 255u;
+            const long long t = (long long)gbase[dd] + (i - (int)loff[dd]);
+            if (t >= 0 && t < n) {
+                dst[k] = (unsigned)t;
+                if (!LAST) keys_out[t] = kk;
+            }
         }
-        __syncthreads();
     }
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < kKeysPerThread; ++j)
         if (lpos[j] != 0xffffffffu) stage[lpos[j]] = val[j];
     __syncthreads();
-    for (int i = tid; i < valid; i += kThreads) {
-        const unsigned dd = st_dig[i];
-        const long long dst = (long long)gbase[dd] + (i - (int)loff[dd]);
-        if (dst >= 0 && dst < n) vals_out[dst] = stage[i];
-    }
+#pragma unroll
+    for (int k = 0; k < kKeysPerThread; ++k)
+        if (dst[k] != 0xffffffffu) vals_out[dst[k]] = stage[tid + k * kThreads];
     if (CARRY) {
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kKeysPerThread; ++j)
             if (lpos[j] != 0xffffffffu) stage[lpos[j]] = __float_as_uint(wt[j]);
         __syncthreads();
-        for (int i = tid; i < valid; i += kThreads) {
-            const unsigned dd = st_dig[i];
-            const long long dst = (long long)gbase[dd] + (i - (int)loff[dd]);
-            if (dst >= 0 && dst < n) w_out[dst] = __uint_as_float(stage[i]);
-        }
+#pragma unroll
+        for (int k = 0; k < kKeysPerThread; ++k)
+            if (dst[k] != 0xffffffffu) w_out[dst[k]] = __uint_as_float(stage[tid + k * kThreads]);
     }
 }
 
@@ -302,9 +334,10 @@ int rank_sort(const amber_plan_s* p, const float* d_J, const float* d_w, unsigne
                        reinterpret_cast<unsigned*>(ws + L.lookback) + 2 * lbw};
 
     AMBER_LAUNCH(p, "rank_init", k_ctrl_init, dim3(1), dim3(256), s, ctrl);
-    const unsigned hist_blocks = (unsigned)std::min<long long>(2048, (n + kThreads * 16 - 1) / (kThreads * 16));
-    AMBER_LAUNCH(p, "rank_hist", k_hist, dim3(hist_blocks), dim3(kThreads), s, d_J, n, ctrl, lb[0], n_tiles * 256);
-    AMBER_LAUNCH(p, "rank_digit_offsets", k_digit_offsets, dim3(1), dim3(kThreads), s, ctrl);
+    const unsigned hist_blocks =
+        (unsigned)std::min<long long>(2048, (n + kHistThreads * 16 - 1) / (kHistThreads * 16));
+    AMBER_LAUNCH(p, "rank_hist", k_hist, dim3(hist_blocks), dim3(kHistThreads), s, d_J, n, ctrl, lb[0], n_tiles * 256);
+    AMBER_LAUNCH(p, "rank_digit_offsets", k_digit_offsets, dim3(1), dim3(256), s, ctrl);
     const dim3 grid((unsigned)n_tiles), blk(kThreads);
     // pass 0: J, w -> buffers 1; pass 1: 1 -> 0; pass 2: 0 -> 1; pass 3: 1 -> 0 (values, weights)
     uint32_t* final_vals = d_perm_out ? d_perm_out : vals[0];
