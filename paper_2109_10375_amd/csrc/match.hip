@@ -12,23 +12,34 @@
 // a fixed operation order and no fused multiply-add, so z_re is a pure function
 // of (J, w, table).
 //
-// One block scans 4096 consecutive ranks: per-thread serial prefix of 16,
-// wave and block scans in registers/LDS, then a decoupled look-back over the
-// preceding tiles for the tile's starting sum (tiles take tickets in launch
-// order, so every wait is on a tile that is already running).
+// Launches: exact sums of every tile of ranks (a streaming reduction that
+// also checks the 127-bit range), their prefix, then one block per tile that
+// matches its ranks and partitions the (cell, z) pairs by cell range; a second
+// partition level and an LDS pass per 16K-cell range put z_re in cell order.
+// No tile waits on another.
 #include <algorithm>
 
 #include "internal.h"
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
-constexpr int kPer = 16;
-constexpr int kTile = kThreads * kPer;
+#ifndef AMBER_SCAN_THREADS
+#define AMBER_SCAN_THREADS 256
+#endif
+constexpr int kPer = 16;                            // ranks (or pairs) per thread
+constexpr int kScanThreads = AMBER_SCAN_THREADS;    // tile sums and matching: one tile per block
+constexpr int kScanWaves = kScanThreads / 64;
+constexpr int kScanTile = kScanThreads * kPer;
+constexpr int kPartThreads = 1024;                  // second partition level: 16384 pairs per block
+constexpr int kPartTile = kPartThreads * kPer;
+#ifndef AMBER_L1_BUCKETS
+#define AMBER_L1_BUCKETS 128
+#endif
+constexpr int kL1 = AMBER_L1_BUCKETS;  // first-level cell-range buckets
+constexpr int kL2 = 65536 / kL1;       // second-level sub-buckets of each bucket
+static_assert(kScanThreads >= 256 && kScanTile <= 65536, "tile geometry");
+static_assert(kL1 >= 64 && kL1 % 64 == 0 && kL1 <= kScanThreads && kL2 <= kPartThreads, "bucket geometry");
 constexpr int kMaxHist = 3;
-constexpr unsigned kAgg = 1u, kPre = 2u;
-constexpr unsigned kPartAgg = kLbAgg, kPartPre = kLbPre, kPartMask = kLbMask;
 constexpr int kGroup = 3;  // histories per scan launch
 
 struct u128 {
@@ -106,9 +117,6 @@ __device__ __forceinline__ long long guess_node(double F, const HistArg& H) {
     return (long long)gg;
 }
 
-struct HistArg;
-__device__ __forceinline__ long long guess_node(double F, const HistArg& H);
-
 // Exact bracket j = max{ j in [0, T] : X_j >= F } (X non-increasing, X_0 = 1),
 // walking from a starting node: the comparisons with the table decide, so the
 // result does not depend on where the walk starts.
@@ -132,15 +140,17 @@ __device__ __forceinline__ double interpolate(const double* __restrict__ X, doub
     return (z < z_top) ? z : z_top;
 }
 
-__device__ __forceinline__ u128 ld128(const unsigned long long* p) {
-    u128 r;
-    r.lo = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    r.hi = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return r;
-}
-__device__ __forceinline__ void st128(unsigned long long* p, u128 v) {
-    __hip_atomic_store(p, v.lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(p + 1, v.hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// The same interpolation with X_j and X_{j+1} already loaded (j <= T - 1).
+__device__ __forceinline__ double interpolate_xy(double F, long long j, double xj, double xj1, double a, double h,
+                                                 double z_top) {
+#pragma clang fp contract(off)
+    const double zj = a + (double)j * h;
+    const double zj1 = a + (double)(j + 1) * h;
+    const double den = xj - xj1;
+    const double t = (den != 0.0) ? (xj - F) / den : 0.0;
+    const double dz = zj1 - zj;
+    const double z = zj + t * dz;
+    return (z < z_top) ? z : z_top;
 }
 
 __device__ __forceinline__ u128 shfl_up128(u128 v, int d) {
@@ -150,8 +160,11 @@ __device__ __forceinline__ u128 shfl_up128(u128 v, int d) {
     return o;
 }
 
-// Exclusive scan of one value per thread over the 256 threads.
-__device__ __forceinline__ unsigned block_excl_scan(unsigned v, unsigned* sh) {
+// Exclusive scan over NB values held by threads 0..NB-1 (NB a multiple of 64);
+// every thread of the block calls it (it contains a barrier), the result is
+// defined for threads 0..NB-1.
+template <int NB>
+__device__ __forceinline__ unsigned bucket_excl_scan(unsigned v, unsigned* sh /* NB / 64 */) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned x = v;
 #pragma unroll
@@ -159,13 +172,12 @@ __device__ __forceinline__ unsigned block_excl_scan(unsigned v, unsigned* sh) {
         const unsigned u = __shfl_up(x, o, 64);
         if (lane >= o) x += u;
     }
-    if (lane == 63) sh[wave] = x;
+    if (wave < NB / 64 && lane == 63) sh[wave] = x;
     __syncthreads();
     unsigned add = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w)
+    for (int w = 0; w < NB / 64; ++w)
         if (w < wave) add += sh[w];
-    __syncthreads();
     return add + x - v;
 }
 
@@ -214,34 +226,43 @@ struct Acc<true> {
     __device__ u128 wide() const { return v; }
 };
 
-// Exact mass of every 4096-rank tile, before any rank is matched: block g sums
-// tiles 64 g .. 64 g + 63 of the sorted weights in order and keeps, per tile,
-// the exclusive prefix within the block (local[tile]) and the block's total.
-// Every weight is also checked: its scaled value m 2^(q - qmin) must fit in
-// 127 bits, and so must every partial sum.
-constexpr int kTilesPerBlock = 64;
+// Exact mass of every tile, before any rank is matched: block g sums tiles
+// kTilesPerBlock g .. kTilesPerBlock (g + 1) - 1 of the sorted weights and
+// keeps, per tile, the exclusive prefix within the block (local[tile]) and the
+// block's total.  Every weight is also checked: its scaled value m 2^(q - qmin)
+// must fit in 127 bits, and so must every partial sum.
+constexpr int kTilesPerBlock = 16;
 
-__global__ __launch_bounds__(kThreads) void k_tile_sums(const float* __restrict__ w_sorted, long long n, Ctrl* ctrl,
+__device__ __forceinline__ u128 add128_checked(u128 a, u128 b, bool& bad) {
+    const u128 t = add128(a, b);
+    bad |= t.hi < a.hi;
+    return t;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_sums(const float* __restrict__ w_sorted, long long n, Ctrl* ctrl,
                                                         u128* __restrict__ local, u128* __restrict__ block_tot,
                                                         long long n_tiles) {
-    __shared__ u128 s_wave[kWaves];
+    __shared__ u128 s_wave[kTilesPerBlock][kScanWaves];
+    __shared__ u128 s_tile[kTilesPerBlock];
     __shared__ int s_bad;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0) s_bad = 0;
     const int qmin = ctrl->qmin;
-    u128 running = {0ull, 0ull};
     bool bad = false;
+    // no barrier inside the loop: each wave keeps its sum per tile
+#pragma unroll 2
     for (int k = 0; k < kTilesPerBlock; ++k) {
         const long long tile = (long long)blockIdx.x * kTilesPerBlock + k;
-        if (tile >= n_tiles) break;
-        const long long p0 = tile * kTile + (long long)tid * kPer;
+        const long long p0 = tile * kScanTile + (long long)tid * kPer;
         u128 sum = {0ull, 0ull};
-        if (p0 < n) {
+        if (tile < n_tiles && p0 < n) {
             const float4* pw = reinterpret_cast<const float4*>(w_sorted + p0);
+            float4 b4[kPer / 4];
+#pragma unroll
+            for (int q = 0; q < kPer / 4; ++q) b4[q] = pw[q];
 #pragma unroll
             for (int q = 0; q < kPer / 4; ++q) {
-                const float4 b4 = pw[q];
-                const float e[4] = {b4.x, b4.y, b4.z, b4.w};
+                const float e[4] = {b4[q].x, b4[q].y, b4[q].z, b4[q].w};
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const unsigned b = __float_as_uint(e[c]);
@@ -249,10 +270,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_sums(const float* __restrict_
                     const unsigned m = (b & 0x7fffffu) | (ex ? 0x800000u : 0u);
                     const int sh = (ex == 0u ? 1 : (int)ex) - 150 - qmin;
                     bad |= sh < 0 || sh + (m ? 32 - __clz(m) : 0) > 127;
-                    const u128 v = scaled_weight(e[c], qmin);
-                    const u128 t = add128(sum, v);
-                    bad |= t.hi < sum.hi;
-                    sum = t;
+                    sum = add128_checked(sum, scaled_weight(e[c], qmin), bad);
                 }
             }
         }
@@ -261,31 +279,30 @@ __global__ __launch_bounds__(kThreads) void k_tile_sums(const float* __restrict_
             u128 w;
             w.lo = __shfl_xor(sum.lo, o, 64);
             w.hi = __shfl_xor(sum.hi, o, 64);
-            const u128 t = add128(sum, w);
-            bad |= t.hi < sum.hi;
-            sum = t;
+            sum = add128_checked(sum, w, bad);
         }
-        if (lane == 0) s_wave[wave] = sum;
-        __syncthreads();
-        if (tid == 0) {
-            u128 t = {0ull, 0ull};
-            for (int w = 0; w < kWaves; ++w) {
-                const u128 u = add128(t, s_wave[w]);
-                bad |= u.hi < t.hi;
-                t = u;
-            }
-            local[tile] = running;
-            const u128 r = add128(running, t);
-            bad |= r.hi < running.hi;
-            running = r;
-        }
-        __syncthreads();
+        if (lane == 0) s_wave[k][wave] = sum;
     }
     if (bad) s_bad = 1;
     __syncthreads();
+    if (tid < kTilesPerBlock) {
+        u128 t = {0ull, 0ull};
+        bool b2 = false;
+        for (int w = 0; w < kScanWaves; ++w) t = add128_checked(t, s_wave[tid][w], b2);
+        s_tile[tid] = t;
+        if (b2) s_bad = 1;
+    }
+    __syncthreads();
     if (tid == 0) {
+        u128 running = {0ull, 0ull};
+        bool b3 = false;
+        for (int k = 0; k < kTilesPerBlock; ++k) {
+            const long long tile = (long long)blockIdx.x * kTilesPerBlock + k;
+            if (tile < n_tiles) local[tile] = running;
+            running = add128_checked(running, s_tile[k], b3);
+        }
         block_tot[blockIdx.x] = running;
-        if (s_bad) atomicOr(&ctrl->status, AMBER_STATUS_RANGE);
+        if (s_bad || b3) atomicOr(&ctrl->status, AMBER_STATUS_RANGE);
     }
 }
 
@@ -300,11 +317,7 @@ __global__ __launch_bounds__(kPrefixThreads) void k_block_prefix(u128* __restric
     const long long b0 = (long long)tid * per;
     u128 sum = {0ull, 0ull};
     bool bad = false;
-    for (long long b = b0; b < b0 + per && b < nb; ++b) {
-        const u128 t = add128(sum, block_tot[b]);
-        bad |= t.hi < sum.hi;
-        sum = t;
-    }
+    for (long long b = b0; b < b0 + per && b < nb; ++b) sum = add128_checked(sum, block_tot[b], bad);
     s_part[tid] = sum;
     __syncthreads();
     if (tid == 0) {
@@ -312,9 +325,7 @@ __global__ __launch_bounds__(kPrefixThreads) void k_block_prefix(u128* __restric
         for (int i = 0; i < kPrefixThreads; ++i) {
             const u128 v = s_part[i];
             s_part[i] = run;
-            const u128 t = add128(run, v);
-            bad |= t.hi < run.hi;
-            run = t;
+            run = add128_checked(run, v, bad);
         }
         ctrl->total_lo = run.lo;
         ctrl->total_hi = run.hi;
@@ -331,44 +342,46 @@ __global__ __launch_bounds__(kPrefixThreads) void k_block_prefix(u128* __restric
     if (bad) atomicOr(&ctrl->status, AMBER_STATUS_RANGE);
 }
 
-// Tile of 4096 consecutive ranks; thread t owns ranks 16 t .. 16 t + 15.
+// One block per tile of kScanTile consecutive ranks; thread t owns ranks
+// 16 t .. 16 t + 15.
 //  1. load cell indices and weights (16-byte vector loads); count the tile's
-//     members of each index-range bucket (bucket b = cells [b S, (b+1) S),
-//     S = n / 256) and scan the thread totals of the exact weights;
-//  2. take its slots in each bucket with one atomic add per bucket; its
-//     starting mass comes from the tile prefix computed beforehand, so no
-//     tile waits on another;
-//  3. four ranks at a time: the exact prefix, F_n = RN(C_n)/RN(C_N), the
-//     bracket for each history from the closed-form guess with all table reads
-//     of the four ranks in flight together, z_n, and the (cell, z) pairs staged
-//     in LDS bucket by bucket and written in coalesced runs.
+//     members of each cell-range bucket (bucket b = cells [b S, (b+1) S),
+//     S = n / kL1) and scan the thread totals of the exact weights;
+//  2. take the tile's slots in each bucket with one atomic add per bucket
+//     (order inside a bucket does not matter); the tile's starting mass comes
+//     from the tile prefixes computed beforehand;
+//  3. F_n for the 16 ranks; the cell indices staged in LDS bucket by bucket,
+//     each thread then takes slots tid + k kScanThreads, keeps their destinations
+//     and writes the cells in runs;
+//  4. per history: z_n (bracket from the closed-form guess, four ranks' table
+//     reads in flight together), staged in the same LDS buffer and written to
+//     the kept destinations.
 // The launch runs the 64-bit variant when the exact total fits in 64 bits and
 // the 128-bit one otherwise (the other variant's blocks return at once).
 // fill[b] (cleared before the launch) counts the slots of bucket b handed out.
 template <int NH, bool WIDE>
-__global__ __launch_bounds__(kThreads) void k_scan_partition(
+__global__ __launch_bounds__(kScanThreads) void k_scan_partition(
     const unsigned* __restrict__ perm, const float* __restrict__ w_sorted, long long n, Ctrl* ctrl,
     const u128* __restrict__ local, const u128* __restrict__ block_excl, unsigned* __restrict__ fill,
     unsigned bucket_size, double bucket_rinv, HistArgs hs, unsigned* __restrict__ part_idx,
     float* __restrict__ part_z0, float* __restrict__ part_z1, float* __restrict__ part_z2) {
     using A = Acc<WIDE>;
     if ((ctrl->wide != 0) != WIDE) return;
-    __shared__ A s_wave[kWaves];
-    __shared__ unsigned lcnt[256];
-    __shared__ unsigned loff[256];
-    __shared__ unsigned gbase[256];
-    __shared__ unsigned scan_sh[kWaves];
-    __shared__ unsigned st_idx[kTile];
-    __shared__ float st_z[NH][kTile];
+    __shared__ A s_wave[kScanWaves];
+    __shared__ unsigned lcnt[kL1];
+    __shared__ unsigned loff[kL1];
+    __shared__ unsigned gbase[kL1];
+    __shared__ unsigned scan_sh[kL1 / 64];
+    __shared__ unsigned stage[kScanTile];  // cells, then z of each history, in bucket order
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    lcnt[tid] = 0u;
+    if (tid < kL1) lcnt[tid] = 0u;
     __syncthreads();
     const long long tile = blockIdx.x;
-    const long long p0 = tile * kTile + (long long)tid * kPer;
+    const long long p0 = tile * kScanTile + (long long)tid * kPer;
     const bool ok = p0 < n;  // n is a multiple of 512: a thread's 16 ranks are all valid or all not
     const int qmin = ctrl->qmin;
 
-    unsigned idx[kPer], rk[kPer];
+    unsigned idx[kPer], rb[kPer];  // rb: bucket << 16 | rank inside the bucket, or ~0
     float wf[kPer];
     if (ok) {
         const uint4* pi = reinterpret_cast<const uint4*>(perm + p0);
@@ -392,7 +405,8 @@ __global__ __launch_bounds__(kThreads) void k_scan_partition(
     for (int j = 0; j < kPer; ++j) {
         const bool live = ok && idx[j] < (unsigned long long)n;
         if (live) tsum = tsum + A::of(wf[j], qmin);
-        rk[j] = live ? atomicAdd(&lcnt[div_exact(idx[j], bucket_size, bucket_rinv)], 1u) : 0xffffffffu;
+        const unsigned b = live ? div_exact(idx[j], bucket_size, bucket_rinv) : 0u;
+        rb[j] = live ? (b << 16) | atomicAdd(&lcnt[b], 1u) : 0xffffffffu;
     }
     // exclusive scan of the thread totals over the wave, then over the waves
     A inc = tsum;
@@ -407,137 +421,191 @@ __global__ __launch_bounds__(kThreads) void k_scan_partition(
     __syncthreads();
     A wave_excl = A::zero();
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w)
+    for (int w = 0; w < kScanWaves; ++w)
         if (w < wave) wave_excl = wave_excl + s_wave[w];
 
-    // this tile's slots in every bucket (any order within a bucket will do);
-    // the atomic's result is only needed when the pairs are written
-    const unsigned cnt = lcnt[tid];
-    const unsigned slot0 = cnt ? atomicAdd(&fill[tid], cnt) : 0u;
-    loff[tid] = block_excl_scan(cnt, scan_sh);
-    __syncthreads();  // every bucket's loff is read below
+    // this tile's slots in every bucket
+    unsigned cnt = 0, slot0 = 0;
+    if (tid < kL1) {
+        cnt = lcnt[tid];
+        slot0 = cnt ? atomicAdd(&fill[tid], cnt) : 0u;
+    }
+    const unsigned lo = bucket_excl_scan<kL1>(cnt, scan_sh);
+    if (tid < kL1) {
+        loff[tid] = lo;
+        gbase[tid] = (unsigned)tid * bucket_size + slot0;
+    }
+    __syncthreads();  // every bucket's loff and gbase are read below
 
     const u128 tile_excl = add128(block_excl[tile / kTilesPerBlock], local[tile]);
     A run = A::of128(tile_excl) + wave_excl + thread_excl;
     const u128 total = {ctrl->total_lo, ctrl->total_hi};
     const double tot = u128_to_f64(total);
-    constexpr int kChunk = 4;
+    double F[kPer];
+    unsigned pos[kPer];
 #pragma unroll
-    for (int c0 = 0; c0 < kPer; c0 += kChunk) {
-        double F[kChunk];
-        unsigned pos[kChunk];
+    for (int j = 0; j < kPer; ++j) {
+        const bool live = rb[j] != 0xffffffffu;
+        if (live) run = run + A::of(wf[j], qmin);
+        F[j] = __ddiv_rn(run.to_f64(), tot);
+        pos[j] = live ? loff[rb[j] >> 16] + (rb[j] & 0xffffu) : 0xffffffffu;
+        if (pos[j] >= (unsigned)kScanTile) pos[j] = 0xffffffffu;  // unreachable for consistent counts
+        if (pos[j] != 0xffffffffu) stage[pos[j]] = idx[j];
+    }
+    __syncthreads();
+    const long long valid_ll = n - tile * kScanTile;
+    const int valid = valid_ll < kScanTile ? (int)valid_ll : kScanTile;
+    unsigned dst[kPer];
 #pragma unroll
-        for (int q = 0; q < kChunk; ++q) {
-            const int j = c0 + q;
-            const bool live = rk[j] != 0xffffffffu;
-            if (live) run = run + A::of(wf[j], qmin);
-            F[q] = __ddiv_rn(run.to_f64(), tot);
-            pos[q] = live ? loff[div_exact(idx[j], bucket_size, bucket_rinv)] + rk[j] : 0xffffffffu;
-            if (pos[q] >= (unsigned)kTile) pos[q] = 0xffffffffu;  // unreachable for consistent counts
-            if (pos[q] != 0xffffffffu) st_idx[pos[q]] = idx[j];
-        }
-#pragma unroll
-        for (int hh = 0; hh < NH; ++hh) {
-            const HistArg& H = hs.h[hh];
-            long long g[kChunk];
-            double x0[kChunk], x1[kChunk];
-#pragma unroll
-            for (int q = 0; q < kChunk; ++q) g[q] = guess_node(F[q], H);
-#pragma unroll
-            for (int q = 0; q < kChunk; ++q) {
-                x0[q] = H.X[g[q]];
-                x1[q] = H.X[g[q] + 1];
-            }
-#pragma unroll
-            for (int q = 0; q < kChunk; ++q) {
-                if (pos[q] == 0xffffffffu) continue;
-                long long jj = g[q];
-                if (!(x0[q] >= F[q] && x1[q] < F[q])) jj = bracket_from(H.X, F[q], jj, H.T);
-                st_z[hh][pos[q]] = (float)interpolate(H.X, F[q], jj, H.a, H.h, H.T, H.z_top);
+    for (int k = 0; k < kPer; ++k) {
+        const int i = tid + k * kScanThreads;
+        dst[k] = 0xffffffffu;
+        if (i < valid) {
+            const unsigned c = stage[i];
+            if (c < (unsigned long long)n) {
+                const unsigned b = div_exact(c, bucket_size, bucket_rinv);
+                const long long t = (long long)gbase[b] + (i - (int)loff[b]);
+                if (t >= 0 && t < n) {  // always, for consistent counts
+                    dst[k] = (unsigned)t;
+                    part_idx[t] = c;
+                }
             }
         }
     }
-    gbase[tid] = (unsigned)tid * bucket_size + slot0;
-    __syncthreads();
-    const long long valid_ll = n - tile * kTile;
-    const int valid = valid_ll < kTile ? (int)valid_ll : kTile;
-    for (int i = tid; i < valid; i += kThreads) {
-        const unsigned c = st_idx[i];
-        if (c >= (unsigned long long)n) continue;
-        const unsigned b = div_exact(c, bucket_size, bucket_rinv);
-        const long long dst = (long long)gbase[b] + (i - (int)loff[b]);
-        if (dst < 0 || dst >= n) continue;  // unreachable for consistent counts
-        part_idx[dst] = c;
-        part_z0[dst] = st_z[0][i];
-        if (NH > 1) part_z1[dst] = st_z[NH > 1 ? 1 : 0][i];
-        if (NH > 2) part_z2[dst] = st_z[NH > 2 ? 2 : 0][i];
+#pragma unroll 1
+    for (int hh = 0; hh < NH; ++hh) {
+        const HistArg& H = hs.h[hh];
+        float* __restrict__ out = hh == 0 ? part_z0 : (hh == 1 ? part_z1 : part_z2);
+        __syncthreads();  // the previous contents of the staging buffer are consumed
+        // A thread's 16 ranks have nearly the same F, so one closed-form guess
+        // (at the middle rank) and one read of the eight table nodes
+        // gl .. gl + 7 around it settle the bracket j = max{ j : X_j >= F }
+        // of every rank with X_gl >= F > X_{gl+7}: j = gl + #{e in 1..6 :
+        // X_{gl+e} >= F}.  Other ranks (the first ranks, where F grows fast
+        // relative to itself) walk exactly from their own guess.  T >= 2^21.
+        long long gl = guess_node(F[kPer / 2], H) - 3;
+        gl = gl < 0 ? 0 : (gl > H.T - 7 ? H.T - 7 : gl);
+        double x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = H.X[gl + e];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            if (pos[j] == 0xffffffffu) continue;
+            const double f = F[j];
+            double z;
+            if (x[0] >= f && x[7] < f) {
+                int kk = 0;
+#pragma unroll
+                for (int e = 1; e < 7; ++e) kk += (x[e] >= f) ? 1 : 0;  // X non-increasing
+                double xj = x[0], xj1 = x[1];
+#pragma unroll
+                for (int e = 1; e < 7; ++e)
+                    if (kk == e) {
+                        xj = x[e];
+                        xj1 = x[e + 1];
+                    }
+                z = interpolate_xy(f, gl + kk, xj, xj1, H.a, H.h, H.z_top);
+            } else {  // the rank's own guess is within a node or two
+                const long long jj = bracket_from(H.X, f, guess_node(f, H), H.T);
+                z = interpolate(H.X, f, jj, H.a, H.h, H.T, H.z_top);
+            }
+            stage[pos[j]] = __float_as_uint((float)z);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPer; ++k)
+            if (dst[k] != 0xffffffffu) out[dst[k]] = __uint_as_float(stage[tid + k * kScanThreads]);
     }
 }
 
 // Second partition level, inside each first-level bucket: the pairs of bucket
-// b (positions [b S1, (b+1) S1), cells of the same range) are split into 256
-// sub-buckets of S2 = S1 / 256 cells.  Tiles never straddle buckets; each tile
+// b (positions [b S1, (b+1) S1), cells of the same range) are split into kL2
+// sub-buckets of S2 = S1 / kL2 cells.  Tiles never straddle buckets; each tile
 // takes its slots in a sub-bucket with one atomic add on that sub-bucket's
 // fill counter (order inside a sub-bucket does not matter).
-__global__ __launch_bounds__(kThreads) void k_partition2(const unsigned* __restrict__ in_idx,
+__global__ __launch_bounds__(kPartThreads) void k_partition2(const unsigned* __restrict__ in_idx,
                                                          const float* __restrict__ in_z, long long n,
                                                          unsigned* __restrict__ fill, unsigned S1, unsigned S2,
-                                                         unsigned tiles_per_bucket,
+                                                         double s2_rinv, unsigned tiles_per_bucket,
                                                          unsigned* __restrict__ out_idx,
                                                          float* __restrict__ out_z) {
-    __shared__ unsigned lcnt[256];
-    __shared__ unsigned loff[256];
-    __shared__ unsigned gbase[256];
-    __shared__ unsigned scan_sh[kWaves];
-    __shared__ unsigned st_idx[kTile];
-    __shared__ float st_z[kTile];
+    __shared__ unsigned lcnt[kL2];
+    __shared__ unsigned loff[kL2];
+    __shared__ unsigned gbase[kL2];
+    __shared__ unsigned scan_sh[kL2 / 64];
+    __shared__ unsigned stage[kPartTile];  // cells, then z, in sub-bucket order
     const int tid = threadIdx.x;
-    lcnt[tid] = 0u;
+    if (tid < kL2) lcnt[tid] = 0u;
     __syncthreads();
     const unsigned tile = blockIdx.x;  // no waits on other tiles
     const unsigned b = tile / tiles_per_bucket, k = tile % tiles_per_bucket;
     const long long bstart = (long long)b * S1;
-    const long long t0 = bstart + (long long)k * kTile;
-    const long long t1 = t0 + kTile < bstart + S1 ? t0 + kTile : bstart + S1;
+    const long long t0 = bstart + (long long)k * kPartTile;
+    const long long t1 = t0 + kPartTile < bstart + S1 ? t0 + kPartTile : bstart + S1;
     const int valid = (int)(t1 - t0);
-    unsigned idx[kPer], sb[kPer], rk[kPer];
+    unsigned idx[kPer], rb[kPer];
     float z[kPer];
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
-        const int i = j * kThreads + tid;
+        const int i = j * kPartThreads + tid;
         const bool ok = i < valid;
         idx[j] = ok ? in_idx[t0 + i] : 0u;
         z[j] = ok ? in_z[t0 + i] : 0.0f;
-        const long long rel = (long long)idx[j] - bstart;
-        const bool live = ok && rel >= 0 && rel < (long long)S1;
-        sb[j] = live ? (unsigned)rel / S2 : 0u;
-        rk[j] = live ? atomicAdd(&lcnt[sb[j]], 1u) : 0xffffffffu;
     }
-    __syncthreads();
-    const unsigned cnt = lcnt[tid];
-    const unsigned slot0 = cnt ? atomicAdd(&fill[(long long)b * 256 + tid], cnt) : 0u;
-    gbase[tid] = (unsigned)(bstart + (long long)tid * S2 + slot0);
-    loff[tid] = block_excl_scan(cnt, scan_sh);
-    __syncthreads();
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
-        if (rk[j] == 0xffffffffu) continue;
-        const unsigned pos = loff[sb[j]] + rk[j];
-        if (pos >= (unsigned)kTile) continue;
-        st_idx[pos] = idx[j];
-        st_z[pos] = z[j];
+        const int i = j * kPartThreads + tid;
+        const long long rel = (long long)idx[j] - bstart;
+        const bool live = i < valid && rel >= 0 && rel < (long long)S1;
+        const unsigned sb = live ? div_exact((unsigned)rel, S2, s2_rinv) : 0u;
+        rb[j] = live ? (sb << 16) | atomicAdd(&lcnt[sb], 1u) : 0xffffffffu;
     }
     __syncthreads();
-    for (int i = tid; i < valid; i += kThreads) {
-        const unsigned c = st_idx[i];
-        const long long rel = (long long)c - bstart;
-        if (rel < 0 || rel >= (long long)S1) continue;
-        const unsigned s2 = (unsigned)rel / S2;
-        const long long dst = (long long)gbase[s2] + (i - (int)loff[s2]);
-        if (dst < 0 || dst >= n) continue;
-        out_idx[dst] = c;
-        out_z[dst] = st_z[i];
+    unsigned cnt = 0, slot0 = 0;
+    if (tid < kL2) {
+        cnt = lcnt[tid];
+        slot0 = cnt ? atomicAdd(&fill[(long long)b * kL2 + tid], cnt) : 0u;
     }
+    const unsigned lo = bucket_excl_scan<kL2>(cnt, scan_sh);
+    if (tid < kL2) {
+        loff[tid] = lo;
+        gbase[tid] = (unsigned)(bstart + (long long)tid * S2 + slot0);
+    }
+    __syncthreads();
+    unsigned pos[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        pos[j] = rb[j] != 0xffffffffu ? loff[rb[j] >> 16] + (rb[j] & 0xffffu) : 0xffffffffu;
+        if (pos[j] >= (unsigned)kPartTile) pos[j] = 0xffffffffu;  // unreachable for consistent counts
+        if (pos[j] != 0xffffffffu) stage[pos[j]] = idx[j];
+    }
+    __syncthreads();
+    unsigned dst[kPer];
+#pragma unroll
+    for (int kk = 0; kk < kPer; ++kk) {
+        const int i = tid + kk * kPartThreads;
+        dst[kk] = 0xffffffffu;
+        if (i < valid) {
+            const unsigned c = stage[i];
+            const long long rel = (long long)c - bstart;
+            if (rel >= 0 && rel < (long long)S1) {
+                const unsigned s2 = div_exact((unsigned)rel, S2, s2_rinv);
+                const long long t = (long long)gbase[s2] + (i - (int)loff[s2]);
+                if (t >= 0 && t < n) {
+                    dst[kk] = (unsigned)t;
+                    out_idx[t] = c;
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPer; ++j)
+        if (pos[j] != 0xffffffffu) stage[pos[j]] = __float_as_uint(z[j]);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kPer; ++kk)
+        if (dst[kk] != 0xffffffffu) out_z[dst[kk]] = __uint_as_float(stage[tid + kk * kPartThreads]);
 }
 
 // Last level: block L owns cells [L S, (L+1) S) (S <= 16384) and exactly the
@@ -561,8 +629,8 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_scatter(const unsigned* _
     for (unsigned i = threadIdx.x; i < S; i += kLeafThreads) out[start + i] = zl[i];
 }
 
-__global__ __launch_bounds__(kThreads) void k_clear(unsigned* __restrict__ p, long long words) {
-    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < words; i += (long long)gridDim.x * kThreads)
+__global__ __launch_bounds__(256) void k_clear(unsigned* __restrict__ p, long long words) {
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < words; i += (long long)gridDim.x * 256)
         p[i] = 0u;
 }
 
@@ -571,7 +639,7 @@ __global__ __launch_bounds__(kThreads) void k_clear(unsigned* __restrict__ p, lo
 int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, float* const* d_zre, unsigned char* ws,
                const WsLayout& L, hipStream_t s) {
     const long long n = (long long)p->n * p->n * p->n;
-    const long long n_tiles = (n + kTile - 1) / kTile;
+    const long long n_tiles = (n + kScanTile - 1) / kScanTile;
     const long long n_blocks = (n_tiles + kTilesPerBlock - 1) / kTilesPerBlock;
     const long long lbw = lb_words(n);  // words per look-back region
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
@@ -591,11 +659,12 @@ int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, flo
     // second level: its own buffers, so the rank order survives for later groups
     unsigned* p2_idx = reinterpret_cast<unsigned*>(ws + L.part2[0]);
     float* p2_z = reinterpret_cast<float*>(ws + L.part2[1]);
-    const unsigned S1 = (unsigned)(n / 256);  // n is a multiple of 512
+    const unsigned S1 = (unsigned)(n / kL1);  // n is a multiple of 512
     const bool two_level = S1 > (unsigned)kLeafMax;
-    const unsigned S2 = two_level ? S1 / 256 : S1;  // divides exactly for the supported sizes
-    const unsigned tpb = (S1 + kTile - 1) / kTile;
-    const dim3 grid((unsigned)n_tiles), blk(kThreads);
+    const unsigned S2 = two_level ? S1 / kL2 : S1;  // divides exactly for the supported sizes
+    const unsigned tpb = (S1 + kPartTile - 1) / kPartTile;
+    const double s2_rinv = 1.0 / (double)S2;
+    const dim3 grid((unsigned)n_tiles), blk(kScanThreads);
 
     AMBER_LAUNCH(p, "match_tile_sums", k_tile_sums, dim3((unsigned)n_blocks), blk, s, w_sorted, n, ctrl, local,
                  block_excl, n_tiles);
@@ -610,7 +679,7 @@ int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, flo
             hs.h[i] = HistArg{w.a_w, w.b_w, 1.0 / w.c_w, w.h, w.z_top, (long long)(w.table_n - 1), w.d_table,
                               d_zre[h0 + i]};
         }
-        if (g > 0) AMBER_LAUNCH(p, "match_clear", k_clear, dim3(1), blk, s, fill1, 256);
+        if (g > 0) AMBER_LAUNCH(p, "match_clear", k_clear, dim3(1), dim3(256), s, fill1, kL1);
 #define AMBER_SCAN(NHV)                                                                                      \
     AMBER_LAUNCH(p, "match_scan_partition", (k_scan_partition<NHV, false>), grid, blk, s, perm, w_sorted, n, \
                  ctrl, local, block_excl, fill1, S1, rinv, hs, p1_idx, p1_z[0], p1_z[1], p1_z[2]);           \
@@ -624,13 +693,13 @@ int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, flo
 #undef AMBER_SCAN
         for (int i = 0; i < hs.n; ++i) {
             if (two_level) {
-                AMBER_LAUNCH(p, "match_clear", k_clear, dim3(256), blk, s, fill2, 65536);
-                AMBER_LAUNCH(p, "match_partition2", k_partition2, dim3(256 * tpb), blk, s, p1_idx, p1_z[i], n, fill2,
-                             S1, S2, tpb, p2_idx, p2_z);
+                AMBER_LAUNCH(p, "match_clear", k_clear, dim3(256), dim3(256), s, fill2, 65536);
+                AMBER_LAUNCH(p, "match_partition2", k_partition2, dim3(kL1 * tpb), dim3(kPartThreads), s, p1_idx, p1_z[i], n, fill2,
+                             S1, S2, s2_rinv, tpb, p2_idx, p2_z);
                 AMBER_LAUNCH(p, "match_leaf_scatter", k_leaf_scatter, dim3((unsigned)(n / S2)), dim3(kLeafThreads), s,
                              p2_idx, p2_z, n, S2, d_zre[h0 + i]);
             } else {
-                AMBER_LAUNCH(p, "match_leaf_scatter", k_leaf_scatter, dim3(256), dim3(kLeafThreads), s, p1_idx,
+                AMBER_LAUNCH(p, "match_leaf_scatter", k_leaf_scatter, dim3(kL1), dim3(kLeafThreads), s, p1_idx,
                              p1_z[i], n, S1, d_zre[h0 + i]);
             }
         }
