@@ -250,7 +250,7 @@ __device__ __forceinline__ int signed_freq(int m, int n) { return (2 * m <= n) ?
 // Column pass.  MODE 0: one transform (INV selects the direction).
 // MODE 1: forward transform, multiply by Khat(|k|)/N^3, inverse transform.
 template <int N, int MODE, bool INV>
-__global__ __launch_bounds__(Shape<N>::C * Shape<N>::N1) void k_fft_cols(
+__global__ __launch_bounds__(Shape<N>::C * Shape<N>::N1, 2) void k_fft_cols(
     const float2* __restrict__ in, float2* __restrict__ out, const float2* __restrict__ tw,
     ColGeom g, MulArgs m) {
     constexpr int N1 = Shape<N>::N1, C = Shape<N>::C, N2 = N / N1;
@@ -348,9 +348,15 @@ __global__ __launch_bounds__(Shape<N>::ZL * Shape<N>::M1) void k_fft_z_c2r(
     const bool live = line < n_lines;
     const float2* irow = main_in + (live ? line : 0) * M;
     float2* mine = lds + l * LS;
+    // all loads in flight before the LDS writes (a dead line reads line 0 and
+    // is never stored)
+    float2 in[M2];
 #pragma unroll
-    for (int j = 0; j < M2; ++j) mine[t + M1 * j] = live ? irow[t + M1 * j] : make_float2(0.f, 0.f);
-    if (t == 0) mine[M] = live ? nyq_in[line] : make_float2(0.f, 0.f);
+    for (int j = 0; j < M2; ++j) in[j] = irow[t + M1 * j];
+    const float2 nq = nyq_in[live ? line : 0];
+#pragma unroll
+    for (int j = 0; j < M2; ++j) mine[t + M1 * j] = in[j];
+    if (t == 0) mine[M] = nq;
     __syncthreads();
     float2 v[M2];
 #pragma unroll

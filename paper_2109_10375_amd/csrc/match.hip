@@ -616,17 +616,31 @@ constexpr int kLeafThreads = 1024;
 __global__ __launch_bounds__(kLeafThreads) void k_leaf_scatter(const unsigned* __restrict__ in_idx,
                                                                const float* __restrict__ in_z, long long n, unsigned S,
                                                                float* __restrict__ out) {
+    constexpr int kR = kLeafMax / kLeafThreads;
     __shared__ float zl[kLeafMax];
     const long long start = (long long)blockIdx.x * S;
-#pragma unroll 4
-    for (unsigned i = threadIdx.x; i < S; i += kLeafThreads) {
-        const unsigned c = in_idx[start + i];
-        const long long rel = (long long)c - start;
-        if (rel >= 0 && rel < (long long)S) zl[rel] = in_z[start + i];
+    unsigned c[kR];
+    float z[kR];
+    // every load in flight before any is used (clamped positions, no branch)
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const unsigned i = threadIdx.x + r * kLeafThreads;
+        const long long at = start + (i < S ? i : 0u);
+        c[r] = in_idx[at];
+        z[r] = in_z[at];
+    }
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const unsigned i = threadIdx.x + r * kLeafThreads;
+        const long long rel = (long long)c[r] - start;
+        if (i < S && rel >= 0 && rel < (long long)S) zl[rel] = z[r];
     }
     __syncthreads();
-#pragma unroll 4
-    for (unsigned i = threadIdx.x; i < S; i += kLeafThreads) out[start + i] = zl[i];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const unsigned i = threadIdx.x + r * kLeafThreads;
+        if (i < S) out[start + i] = zl[i];
+    }
 }
 
 __global__ __launch_bounds__(256) void k_clear(unsigned* __restrict__ p, long long words) {

@@ -93,16 +93,30 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const float* __restrict__
         }
 #pragma unroll
         for (int k = 0; k < kV; ++k) {
-            if (base + k * kHistThreads + threadIdx.x >= n4) continue;
+            const bool live = base + k * kHistThreads + threadIdx.x < n4;
             const float f[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                nan |= is_nan_bits(__float_as_uint(f[e]));
                 const unsigned key = desc_key(f[e]);
-                atomicAdd(&h[wave][0][key & 255u], 1u);
-                atomicAdd(&h[wave][1][(key >> 8) & 255u], 1u);
-                atomicAdd(&h[wave][2][(key >> 16) & 255u], 1u);
-                atomicAdd(&h[wave][3][key >> 24], 1u);
+                if (live) {
+                    nan |= is_nan_bits(__float_as_uint(f[e]));
+                    atomicAdd(&h[wave][0][key & 255u], 1u);
+                    atomicAdd(&h[wave][1][(key >> 8) & 255u], 1u);
+                    atomicAdd(&h[wave][2][(key >> 16) & 255u], 1u);
+                }
+                // The top digit (sign and exponent) takes few values among
+                // neighbouring cells: the lanes sharing it find each other with
+                // 8 ballots and the lowest of them adds the count once.
+                const unsigned d3 = key >> 24;
+                unsigned long long peers = __ballot(live);
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const unsigned long long m = __ballot((d3 >> b) & 1u);
+                    peers &= ((d3 >> b) & 1u) ? m : ~m;
+                }
+                const int lane = threadIdx.x & 63;
+                if (live && (peers & ((1ull << lane) - 1ull)) == 0ull)
+                    atomicAdd(&h[wave][3][d3], (unsigned)__popcll(peers));
             }
         }
     }
@@ -141,16 +155,35 @@ __device__ __forceinline__ int weight_q(unsigned bits) {
     return (e == 0 ? 1 : e) - 150;
 }
 
+// Smallest ulp exponent over the tiles' values (one block).
+__global__ __launch_bounds__(1024) void k_qmin(const int* __restrict__ qtile, long long n_tiles, Ctrl* ctrl) {
+    __shared__ int sh[16];
+    int q = 0x7fffffff;
+    for (long long t = threadIdx.x; t < n_tiles; t += 1024) q = qtile[t] < q ? qtile[t] : q;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int oq = __shfl_xor(q, o, 64);
+        q = oq < q ? oq : q;
+    }
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 16; ++w) q = sh[w] < q ? sh[w] : q;
+        q = sh[0] < q ? sh[0] : q;
+        ctrl->qmin = q;
+    }
+}
+
 // One digit pass over tiles of kTile keys.  FIRST: keys come from J and the
 // index is the position.  LAST: only the values (and weights) are written.
-// CARRY: weights travel with the keys; pass 0 also checks them and finds the
-// smallest ulp exponent.
+// CARRY: weights travel with the keys; pass 0 also checks them and stores the
+// smallest ulp exponent of each tile in qtile[tile].
 template <bool FIRST, bool LAST, bool CARRY>
 __global__ __launch_bounds__(kThreads) void k_onesweep(
     const float* __restrict__ J, const unsigned* __restrict__ keys_in, const unsigned* __restrict__ vals_in,
     const float* __restrict__ w_in, unsigned* __restrict__ keys_out, unsigned* __restrict__ vals_out,
     float* __restrict__ w_out, unsigned* __restrict__ lb, unsigned* __restrict__ lb_next,
-    unsigned* __restrict__ lb_next2, Ctrl* ctrl, int pass, long long n) {
+    unsigned* __restrict__ lb_next2, int* __restrict__ qtile, Ctrl* ctrl, int pass, long long n) {
     __shared__ unsigned s_tile;
     __shared__ unsigned short wcnt[kWaves][256];  // per-wave digit counts, then wave offsets
     __shared__ unsigned loff[256];                // tile-local start of each digit
@@ -178,26 +211,32 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     bool bad_w = false;
     int qmin = 0x7fffffff;
     const long long wbase = tile_base + (long long)wave * (64 * kKeysPerThread);
+    // All loads first, from clamped positions (no branch around a load, so
+    // they are all in flight together); out-of-range lanes are masked after.
 #pragma unroll
     for (int j = 0; j < kKeysPerThread; ++j) {
         const long long pos = wbase + 64 * j + lane;
-        const bool ok = pos < n;
+        const long long pc = pos < n ? pos : n - 1;
         if (FIRST) {
-            key[j] = ok ? desc_key(J[pos]) : 0xffffffffu;
+            key[j] = __float_as_uint(J[pc]);
             val[j] = (unsigned)pos;
         } else {
-            key[j] = ok ? keys_in[pos] : 0xffffffffu;
-            val[j] = ok ? vals_in[pos] : 0u;
+            key[j] = keys_in[pc];
+            val[j] = vals_in[pc];
         }
-        if (CARRY) {
-            wt[j] = ok ? w_in[pos] : 1.0f;
-            if (FIRST && ok) {
-                const unsigned b = __float_as_uint(wt[j]);
-                const bool good = (b - 1u) < 0x7f7fffffu;  // 0 < w < inf, not NaN
-                bad_w |= !good;
-                const int q = weight_q(b);
-                qmin = q < qmin ? q : qmin;
-            }
+        if (CARRY) wt[j] = w_in[pc];
+    }
+#pragma unroll
+    for (int j = 0; j < kKeysPerThread; ++j) {
+        const bool ok = wbase + 64 * j + lane < n;
+        if (FIRST) key[j] = desc_key(__uint_as_float(key[j]));
+        if (!ok) key[j] = 0xffffffffu;
+        if (CARRY && FIRST && ok) {
+            const unsigned b = __float_as_uint(wt[j]);
+            const bool good = (b - 1u) < 0x7f7fffffu;  // 0 < w < inf, not NaN
+            bad_w |= !good;
+            const int q = weight_q(b);
+            qmin = q < qmin ? q : qmin;
         }
     }
 
@@ -262,10 +301,10 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
         if (__any(bad_w) && lane == 0) atomicOr(&ctrl->status, AMBER_STATUS_BAD_W);
     }
     __syncthreads();
-    if (CARRY && FIRST && tid == 0) {
+    if (CARRY && FIRST && tid == 0) {  // a plain store: nothing in this block waits on it
         int q = s_qmin[0];
         for (int w = 1; w < kWaves; ++w) q = s_qmin[w] < q ? s_qmin[w] : q;
-        if (q < __hip_atomic_load(&ctrl->qmin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(&ctrl->qmin, q);
+        qtile[tile] = q;
     }
 
     // Stage the keys in digit order; every thread then takes the slots
@@ -341,24 +380,28 @@ int rank_sort(const amber_plan_s* p, const float* d_J, const float* d_w, unsigne
     const dim3 grid((unsigned)n_tiles), blk(kThreads);
     // pass 0: J, w -> buffers 1; pass 1: 1 -> 0; pass 2: 0 -> 1; pass 3: 1 -> 0 (values, weights)
     uint32_t* final_vals = d_perm_out ? d_perm_out : vals[0];
+    // the per-tile ulp exponents of pass 0 live in the third look-back region
+    // until the last pass clears it
+    int* qtile = reinterpret_cast<int*>(lb[2]);
     if (carry) {
         AMBER_LAUNCH(p, "rank_pass0", (k_onesweep<true, false, true>), grid, blk, s, d_J, nullptr, nullptr, d_w, keys[1],
-                           vals[1], wts[1], lb[0], lb[1], nullptr, ctrl, 0, n);
+                     vals[1], wts[1], lb[0], lb[1], nullptr, qtile, ctrl, 0, n);
+        AMBER_LAUNCH(p, "rank_qmin", k_qmin, dim3(1), dim3(1024), s, qtile, n_tiles, ctrl);
         AMBER_LAUNCH(p, "rank_pass1", (k_onesweep<false, false, true>), grid, blk, s, nullptr, keys[1], vals[1], wts[1],
-                           keys[0], vals[0], wts[0], lb[1], lb[0], nullptr, ctrl, 1, n);
+                     keys[0], vals[0], wts[0], lb[1], lb[0], nullptr, nullptr, ctrl, 1, n);
         AMBER_LAUNCH(p, "rank_pass2", (k_onesweep<false, false, true>), grid, blk, s, nullptr, keys[0], vals[0], wts[0],
-                           keys[1], vals[1], wts[1], lb[0], lb[1], nullptr, ctrl, 2, n);
+                     keys[1], vals[1], wts[1], lb[0], lb[1], nullptr, nullptr, ctrl, 2, n);
         AMBER_LAUNCH(p, "rank_pass3", (k_onesweep<false, true, true>), grid, blk, s, nullptr, keys[1], vals[1], wts[1],
-                           nullptr, final_vals, wts[0], lb[1], lb[0], lb[2], ctrl, 3, n);
+                     nullptr, final_vals, wts[0], lb[1], lb[0], lb[2], nullptr, ctrl, 3, n);
     } else {
-        AMBER_LAUNCH(p, "rank_pass0", (k_onesweep<true, false, false>), grid, blk, s, d_J, nullptr, nullptr, nullptr, keys[1],
-                           vals[1], nullptr, lb[0], lb[1], nullptr, ctrl, 0, n);
-        AMBER_LAUNCH(p, "rank_pass1", (k_onesweep<false, false, false>), grid, blk, s, nullptr, keys[1], vals[1], nullptr,
-                           keys[0], vals[0], nullptr, lb[1], lb[0], nullptr, ctrl, 1, n);
-        AMBER_LAUNCH(p, "rank_pass2", (k_onesweep<false, false, false>), grid, blk, s, nullptr, keys[0], vals[0], nullptr,
-                           keys[1], vals[1], nullptr, lb[0], lb[1], nullptr, ctrl, 2, n);
-        AMBER_LAUNCH(p, "rank_pass3", (k_onesweep<false, true, false>), grid, blk, s, nullptr, keys[1], vals[1], nullptr,
-                           nullptr, final_vals, nullptr, lb[1], lb[0], lb[2], ctrl, 3, n);
+        AMBER_LAUNCH(p, "rank_pass0", (k_onesweep<true, false, false>), grid, blk, s, d_J, nullptr, nullptr, nullptr,
+                     keys[1], vals[1], nullptr, lb[0], lb[1], nullptr, nullptr, ctrl, 0, n);
+        AMBER_LAUNCH(p, "rank_pass1", (k_onesweep<false, false, false>), grid, blk, s, nullptr, keys[1], vals[1],
+                     nullptr, keys[0], vals[0], nullptr, lb[1], lb[0], nullptr, nullptr, ctrl, 1, n);
+        AMBER_LAUNCH(p, "rank_pass2", (k_onesweep<false, false, false>), grid, blk, s, nullptr, keys[0], vals[0],
+                     nullptr, keys[1], vals[1], nullptr, lb[0], lb[1], nullptr, nullptr, ctrl, 2, n);
+        AMBER_LAUNCH(p, "rank_pass3", (k_onesweep<false, true, false>), grid, blk, s, nullptr, keys[1], vals[1],
+                     nullptr, nullptr, final_vals, nullptr, lb[1], lb[0], lb[2], nullptr, ctrl, 3, n);
     }
     AMBER_HIP_CHECK(hipGetLastError());
     return AMBER_OK;
