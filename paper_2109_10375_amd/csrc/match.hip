@@ -455,6 +455,56 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
     __syncthreads();
     const long long valid_ll = n - tile * kScanTile;
     const int valid = valid_ll < kScanTile ? (int)valid_ll : kScanTile;
+    // A thread's 16 ranks have nearly the same F, so one closed-form guess (at
+    // the middle rank) and one read of the eight table nodes gl .. gl + 7
+    // around it settle the bracket j = max{ j : X_j >= F } of every rank with
+    // X_gl >= F > X_{gl+7}: j = gl + #{e in 1..6 : X_{gl+e} >= F}.  Other ranks
+    // (the first ranks, where F grows fast relative to itself) walk exactly
+    // from their own guess.  T >= 2^21.
+    auto window = [&](const HistArg& H, long long& gl, double* x) {
+        gl = guess_node(F[kPer / 2], H) - 3;
+        gl = gl < 0 ? 0 : (gl > H.T - 7 ? H.T - 7 : gl);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = H.X[gl + e];
+    };
+    // z of the thread's ranks for one history
+    auto z_of = [&](const HistArg& H, long long gl, const double* x, float* zf) {
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const double f = F[j];
+            double z = 0.0;
+            if (pos[j] != 0xffffffffu) {
+                if (x[0] >= f && x[7] < f) {
+                    int kk = 0;
+#pragma unroll
+                    for (int e = 1; e < 7; ++e) kk += (x[e] >= f) ? 1 : 0;  // X non-increasing
+                    double xj = x[0], xj1 = x[1];
+#pragma unroll
+                    for (int e = 1; e < 7; ++e)
+                        if (kk == e) {
+                            xj = x[e];
+                            xj1 = x[e + 1];
+                        }
+                    z = interpolate_xy(f, gl + kk, xj, xj1, H.a, H.h, H.z_top);
+                } else {
+                    const long long jj = bracket_from(H.X, f, guess_node(f, H), H.T);
+                    z = interpolate(H.X, f, jj, H.a, H.h, H.T, H.z_top);
+                }
+            }
+            zf[j] = (float)z;
+        }
+    };
+    // The first history's z is computed before any store is issued: a wait
+    // for a load issued before stores that may or may not execute would also
+    // wait for those stores.
+    float zf0[kPer];
+    {
+        long long gl0;
+        double x0[8];
+        window(hs.h[0], gl0, x0);
+        z_of(hs.h[0], gl0, x0, zf0);
+    }
+
     unsigned dst[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -477,39 +527,19 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
         const HistArg& H = hs.h[hh];
         float* __restrict__ out = hh == 0 ? part_z0 : (hh == 1 ? part_z1 : part_z2);
         __syncthreads();  // the previous contents of the staging buffer are consumed
-        // A thread's 16 ranks have nearly the same F, so one closed-form guess
-        // (at the middle rank) and one read of the eight table nodes
-        // gl .. gl + 7 around it settle the bracket j = max{ j : X_j >= F }
-        // of every rank with X_gl >= F > X_{gl+7}: j = gl + #{e in 1..6 :
-        // X_{gl+e} >= F}.  Other ranks (the first ranks, where F grows fast
-        // relative to itself) walk exactly from their own guess.  T >= 2^21.
-        long long gl = guess_node(F[kPer / 2], H) - 3;
-        gl = gl < 0 ? 0 : (gl > H.T - 7 ? H.T - 7 : gl);
-        double x[8];
+        if (hh == 0) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = H.X[gl + e];
+            for (int j = 0; j < kPer; ++j)
+                if (pos[j] != 0xffffffffu) stage[pos[j]] = __float_as_uint(zf0[j]);
+        } else {
+            long long gl;
+            double x[8];
+            float zf[kPer];
+            window(H, gl, x);
+            z_of(H, gl, x, zf);
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            if (pos[j] == 0xffffffffu) continue;
-            const double f = F[j];
-            double z;
-            if (x[0] >= f && x[7] < f) {
-                int kk = 0;
-#pragma unroll
-                for (int e = 1; e < 7; ++e) kk += (x[e] >= f) ? 1 : 0;  // X non-increasing
-                double xj = x[0], xj1 = x[1];
-#pragma unroll
-                for (int e = 1; e < 7; ++e)
-                    if (kk == e) {
-                        xj = x[e];
-                        xj1 = x[e + 1];
-                    }
-                z = interpolate_xy(f, gl + kk, xj, xj1, H.a, H.h, H.z_top);
-            } else {  // the rank's own guess is within a node or two
-                const long long jj = bracket_from(H.X, f, guess_node(f, H), H.T);
-                z = interpolate(H.X, f, jj, H.a, H.h, H.T, H.z_top);
-            }
-            stage[pos[j]] = __float_as_uint((float)z);
+            for (int j = 0; j < kPer; ++j)
+                if (pos[j] != 0xffffffffu) stage[pos[j]] = __float_as_uint(zf[j]);
         }
         __syncthreads();
 #pragma unroll

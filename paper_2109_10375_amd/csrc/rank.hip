@@ -307,6 +307,12 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
         qtile[tile] = q;
     }
 
+    // Every load of this tile has arrived by now (the keys were ranked, the
+    // look-back is done); saying so keeps the compiler from waiting on the
+    // stores issued below before each later LDS staging step (the vector
+    // memory counter counts loads and stores together).
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt unconstrained
+
     // Stage the keys in digit order; every thread then takes the slots
     // tid + k kThreads, finds each slot's destination from the staged key's
     // digit, and keeps it for the indices and weights staged after it.
