@@ -153,6 +153,39 @@ int amber_zre(amber_plan plan, const float* d_J, const float* d_w,
  * last calls that used this workspace in *status. */
 int amber_status(amber_plan plan, void* d_ws, void* stream, unsigned* status);
 
+/* ---- batches (several boxes, mean free paths and histories) ------------- */
+
+/* One box of a batch: the radiation field for each of its n_lmfp mean free
+ * paths (Sec. 3.4.1), then abundance matching of every J against each of its
+ * n_hist histories (Sec. 3.4.2), exactly as amber_radiation followed by one
+ * amber_zre per J.  Boxes may have different plans (sizes). */
+typedef struct {
+    amber_plan plan;             /* grid size and box side of this box                     */
+    const float* d_src;          /* N^3 source field; NULL: d_J already holds the fields   */
+    const float* d_w;            /* N^3 gas-mass weights (1 + delta, > 0)                  */
+    int n_lmfp;                  /* 1..64                                                  */
+    const double* l_mfp;         /* host array of n_lmfp mean free paths (unused if no src) */
+    float* const* d_J;           /* host array of n_lmfp device pointers to N^3 FP32       */
+    int n_hist;                  /* 1..8                                                   */
+    const amber_weibull* hist;   /* host array of n_hist fitted histories (device tables)  */
+    float* const* d_zre;         /* host array of n_lmfp * n_hist device pointers, entry
+                                    l * n_hist + h is z_re of J_l under history h          */
+} amber_batch_item;
+
+/* Workspace for amber_batch_run over these items: the largest single-box
+ * requirement (boxes run one after another and share it). 0 on bad input. */
+size_t amber_batch_workspace_bytes(const amber_batch_item* items, int n_items);
+
+/* Enqueues every box of the batch on `stream`, in order.  All items are
+ * checked on the host before anything is enqueued (the first error is
+ * returned and nothing runs).  d_status (optional, device, n_items unsigned)
+ * receives the OR of each box's device status bits (AMBER_STATUS_*).  Only
+ * kernels are enqueued (no allocation, copy, memset or synchronisation), so a
+ * batch can be captured into a HIP graph and replayed; per-kernel timing
+ * (amber_profile_begin) must be off while capturing. */
+int amber_batch_run(const amber_batch_item* items, int n_items, unsigned* d_status, void* d_ws, size_t ws_bytes,
+                    void* stream);
+
 /* ---- per-kernel timing (tracing aid, not needed for results) ------------ */
 
 typedef struct {

@@ -5,8 +5,12 @@ the method's arithmetic: it only draws density, source and intensity fields
 with the structure of the paper's workloads (see ``synth.py``).
 """
 from .synth import (  # noqa: F401
+    C3_HISTORIES,
+    C3_LMFP,
     CONFIGS,
     BoxConfig,
+    c4_boxes,
+    c5_requests,
     config_seed,
     make_box,
     make_density,

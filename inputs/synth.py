@@ -206,3 +206,47 @@ def make_weights_edge(n3: int, seed: int, kind: str, device="cpu") -> torch.Tens
         w[pick[k // 2:]] = torch.tensor(1.4e-45, dtype=torch.float32)    # the smallest one
         return w
     raise ValueError(kind)
+
+
+# ------------------------------------------------------------------------
+# Mixed-size batches and a request stream (the batched and served workloads).
+
+C4_SIZES = (64, 96, 128, 192, 256)
+C3_LMFP = CONFIGS["c3"].l_mfp
+C3_HISTORIES = CONFIGS["c3"].histories
+
+
+def c4_boxes(count: int = 64, seed: int = 4, sizes=C4_SIZES):
+    """``count`` boxes with N drawn uniformly from ``sizes``, L = 1.953125 N
+    h^-1 Mpc, 1.3M (N/256)^3 halos on [1e10, 1e12], l_mfp ~ U[1, 20] and a
+    history with z_mid ~ U[6, 10], Delta_z ~ U[2, 6], A_z ~ U[1.5, 4]."""
+    g = torch.Generator().manual_seed(config_seed(seed, 0))
+    out = []
+    for b in range(count):
+        n = sizes[int(torch.randint(0, len(sizes), (1,), generator=g))]
+        u = torch.rand(4, generator=g, dtype=torch.float64).tolist()
+        l = 1.0 + 19.0 * u[0]
+        hist = (6.0 + 4.0 * u[1], 2.0 + 4.0 * u[2], 1.5 + 2.5 * u[3])
+        out.append(BoxConfig(f"c4.{b}", n, 1.953125 * n, max(1000, int(1.3e6 * (n / 256) ** 3)), 1e10, 1e12,
+                             l_mfp=(l,), histories=(hist,), index=100 + b))
+    return out
+
+
+def c5_requests(duration_s: float, rate_hz: float = 20.0, seed: int = 5, sizes=(128, 256, 512, 1024),
+                weights=(0.4, 0.3, 0.2, 0.1)):
+    """Poisson request stream: arrival times (exponential gaps at ``rate_hz``)
+    over ``duration_s`` seconds, each with N drawn with ``weights`` and an
+    l_mfp and history drawn from the swept sets of the 512^3 configuration."""
+    g = torch.Generator().manual_seed(config_seed(seed, 0))
+    cw = torch.tensor(weights, dtype=torch.float64).cumsum(0)
+    t, reqs = 0.0, []
+    while True:
+        t += float(-math.log(1.0 - float(torch.rand(1, generator=g, dtype=torch.float64))) / rate_hz)
+        if t >= duration_s:
+            break
+        u = float(torch.rand(1, generator=g, dtype=torch.float64)) * float(cw[-1])
+        n = sizes[int((cw < u).sum())]
+        li = int(torch.randint(0, len(C3_LMFP), (1,), generator=g))
+        hi = int(torch.randint(0, len(C3_HISTORIES), (1,), generator=g))
+        reqs.append((t, n, C3_LMFP[li], C3_HISTORIES[hi]))
+    return reqs

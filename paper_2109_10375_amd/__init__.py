@@ -8,6 +8,8 @@ the library is missing, every call raises.
 """
 from ._lib import (  # noqa: F401
     AmberError,
+    Batch,
+    BatchItem,
     History,
     Plan,
     STATUS_BAD_W,
@@ -17,5 +19,5 @@ from ._lib import (  # noqa: F401
     library_path,
 )
 
-__all__ = ["AmberError", "History", "Plan", "lib", "library_path",
+__all__ = ["AmberError", "Batch", "BatchItem", "History", "Plan", "lib", "library_path",
            "STATUS_NAN_J", "STATUS_BAD_W", "STATUS_RANGE"]

@@ -23,7 +23,7 @@ SYMBOLS = [
     "amber_version", "amber_strerror", "amber_weibull_fit", "amber_weibull_from_coeffs",
     "amber_weibull_table", "amber_plan_create", "amber_plan_destroy", "amber_workspace_bytes",
     "amber_radiation", "amber_rank", "amber_zre", "amber_status", "amber_profile_begin",
-    "amber_profile_end",
+    "amber_profile_end", "amber_batch_workspace_bytes", "amber_batch_run",
 ]
 
 
@@ -40,6 +40,13 @@ class AmberKernelTime(ctypes.Structure):
 class AmberHistory(ctypes.Structure):
     _fields_ = [("z_mid", ctypes.c_double), ("delta_z", ctypes.c_double), ("a_z", ctypes.c_double),
                 ("x_ear", ctypes.c_double), ("x_mid", ctypes.c_double), ("x_lat", ctypes.c_double)]
+
+
+class AmberBatchItem(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("d_src", ctypes.c_void_p), ("d_w", ctypes.c_void_p),
+                ("n_lmfp", ctypes.c_int), ("l_mfp", ctypes.POINTER(ctypes.c_double)),
+                ("d_J", ctypes.POINTER(ctypes.c_void_p)), ("n_hist", ctypes.c_int),
+                ("hist", ctypes.POINTER(AmberWeibull)), ("d_zre", ctypes.POINTER(ctypes.c_void_p))]
 
 
 class AmberError(RuntimeError):
@@ -82,6 +89,9 @@ def lib() -> ctypes.CDLL:
         L.amber_status.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_uint)]
         L.amber_profile_begin.argtypes = [vp, i]
         L.amber_profile_end.argtypes = [vp, ctypes.POINTER(AmberKernelTime), i, ctypes.POINTER(i)]
+        L.amber_batch_workspace_bytes.argtypes = [ctypes.POINTER(AmberBatchItem), i]
+        L.amber_batch_workspace_bytes.restype = sz
+        L.amber_batch_run.argtypes = [ctypes.POINTER(AmberBatchItem), i, vp, vp, sz, vp]
         _lib = L
     return _lib
 
@@ -222,3 +232,49 @@ class Plan:
         _check(lib().amber_status(self._h, ctypes.c_void_p(ws.data_ptr()), _stream(), ctypes.byref(v)),
                "amber_status")
         return int(v.value)
+
+
+class BatchItem:
+    """One box of a batch (amber_batch_item): its fields, mean free paths and
+    histories.  z_re of J_l under history h is zre[l][h]."""
+
+    def __init__(self, plan: Plan, S: torch.Tensor | None, w: torch.Tensor, l_mfp: Sequence[float],
+                 J: Sequence[torch.Tensor], hists: Sequence[History], zre: Sequence[Sequence[torch.Tensor]]):
+        nl, nh = len(J), len(hists)
+        if S is not None and len(l_mfp) != nl:
+            raise ValueError("one J field per mean free path")
+        if len(zre) != nl or any(len(row) != nh for row in zre):
+            raise ValueError("zre must hold n_lmfp rows of n_hist fields")
+        self.plan, self.S, self.w, self.J, self.hists, self.zre = plan, S, w, list(J), list(hists), zre
+        n3 = plan.n3
+        self._l = (ctypes.c_double * max(1, nl))(*[float(x) for x in l_mfp] if S is not None else [])
+        self._J = (ctypes.c_void_p * nl)(*[_dev_ptr(t, torch.float32, n3, "J").value for t in J])
+        self._h = (AmberWeibull * nh)(*[h.w for h in hists])
+        flat = [z for row in zre for z in row]
+        self._z = (ctypes.c_void_p * len(flat))(*[_dev_ptr(t, torch.float32, n3, "z_re").value for t in flat])
+        self.c = AmberBatchItem(plan._h.value, _dev_ptr(S, torch.float32, n3, "S").value if S is not None else None,
+                                _dev_ptr(w, torch.float32, n3, "w").value, nl,
+                                ctypes.cast(self._l, ctypes.POINTER(ctypes.c_double)),
+                                ctypes.cast(self._J, ctypes.POINTER(ctypes.c_void_p)), nh,
+                                ctypes.cast(self._h, ctypes.POINTER(AmberWeibull)),
+                                ctypes.cast(self._z, ctypes.POINTER(ctypes.c_void_p)))
+
+
+class Batch:
+    """A fixed list of boxes run by amber_batch_run with one shared workspace."""
+
+    def __init__(self, items: Sequence[BatchItem]):
+        self.items = list(items)
+        self._arr = (AmberBatchItem * len(self.items))(*[it.c for it in self.items])
+        need = int(lib().amber_batch_workspace_bytes(self._arr, len(self.items)))
+        if need == 0:
+            raise ValueError("invalid batch")
+        self.device = self.items[0].plan.device
+        self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        self.status = torch.zeros(len(self.items), dtype=torch.int32, device=self.device)
+
+    def run(self) -> None:
+        """amber_batch_run on torch's current stream; per-box status bits land in self.status."""
+        _check(lib().amber_batch_run(self._arr, len(self.items), ctypes.c_void_p(self.status.data_ptr()),
+                                     ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream()),
+               "amber_batch_run")

@@ -337,6 +337,72 @@ int amber_zre(amber_plan plan, const float* d_J, const float* d_w, const amber_w
     return match_scan(plan, hist, n_hist, d_zre, ws, L, s);
 }
 
+static int check_item(const amber_batch_item& it) {
+    if (!it.plan || !it.d_w || !it.d_J || !it.d_zre || !it.hist) return AMBER_E_ARG;
+    if (it.n_lmfp < 1 || it.n_lmfp > 64 || it.n_hist < 1 || it.n_hist > 8) return AMBER_E_ARG;
+    for (int i = 0; i < it.n_lmfp; ++i) {
+        if (!it.d_J[i]) return AMBER_E_ARG;
+        if (it.d_src) {
+            if (!it.l_mfp || !(it.l_mfp[i] > 0.0) || !std::isfinite(it.l_mfp[i])) return AMBER_E_ARG;
+            if ((const void*)it.d_J[i] == (const void*)it.d_src) return AMBER_E_ARG;
+        }
+    }
+    for (int i = 0; i < it.n_lmfp * it.n_hist; ++i)
+        if (!it.d_zre[i]) return AMBER_E_ARG;
+    for (int h = 0; h < it.n_hist; ++h) {
+        const amber_weibull& w = it.hist[h];
+        if (!w.d_table || w.table_n < 2) return AMBER_E_ARG;
+        if (!(w.a_w > 0.0) || !(w.b_w > 0.0) || !(w.c_w > 0.0) || !(w.h > 0.0) || !(w.z_top > w.a_w) ||
+            !std::isfinite(w.z_top))
+            return AMBER_E_HISTORY;
+    }
+    return AMBER_OK;
+}
+
+size_t amber_batch_workspace_bytes(const amber_batch_item* items, int n_items) {
+    if (!items || n_items < 1) return 0;
+    size_t need = 0;
+    for (int i = 0; i < n_items; ++i) {
+        if (!items[i].plan) return 0;
+        const int nl = items[i].d_src ? std::max(1, items[i].n_lmfp) : 1;
+        need = std::max(need, ws_layout(items[i].plan->n, nl).total);
+    }
+    return need;
+}
+
+int amber_batch_run(const amber_batch_item* items, int n_items, unsigned* d_status, void* d_ws, size_t ws_bytes,
+                    void* stream) {
+    if (!items || n_items < 1 || !d_ws) return AMBER_E_ARG;
+    for (int i = 0; i < n_items; ++i) {
+        const int rc = check_item(items[i]);
+        if (rc != AMBER_OK) return rc;
+    }
+    if (ws_bytes < amber_batch_workspace_bytes(items, n_items)) return AMBER_E_WORKSPACE;
+    unsigned char* ws = static_cast<unsigned char*>(d_ws);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < n_items; ++i) {
+        const amber_batch_item& it = items[i];
+        const amber_plan_s* p = it.plan;
+        if (it.d_src) {
+            const WsLayout LR = ws_layout(p->n, it.n_lmfp);
+            const int rc = fft_radiation(p, it.d_src, it.l_mfp, it.n_lmfp, it.d_J, ws, LR, s);
+            if (rc != AMBER_OK) return rc;
+        }
+        const WsLayout L = ws_layout(p->n, 1);
+        if (d_status) {
+            const int rc = status_collect(p, ws, L, d_status + i, true, s);
+            if (rc != AMBER_OK) return rc;
+        }
+        for (int l = 0; l < it.n_lmfp; ++l) {
+            int rc = rank_sort(p, it.d_J[l], it.d_w, ws, L, s, 1, nullptr);
+            if (rc == AMBER_OK) rc = match_scan(p, it.hist, it.n_hist, it.d_zre + (size_t)l * it.n_hist, ws, L, s);
+            if (rc == AMBER_OK && d_status) rc = status_collect(p, ws, L, d_status + i, false, s);
+            if (rc != AMBER_OK) return rc;
+        }
+    }
+    return AMBER_OK;
+}
+
 int amber_status(amber_plan plan, void* d_ws, void* stream, unsigned* status) {
     if (!plan || !d_ws || !status) return AMBER_E_ARG;
     const WsLayout L = ws_layout(plan->n, 1);

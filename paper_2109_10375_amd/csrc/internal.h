@@ -134,6 +134,9 @@ int rank_sort(const amber_plan_s* p, const float* d_J, const float* d_w, unsigne
               const WsLayout& L, hipStream_t s, int carry_weights, uint32_t* d_perm_out);
 int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, float* const* d_zre,
                unsigned char* ws, const WsLayout& L, hipStream_t s);
+// dst[0] = 0 (first) or dst[0] |= the status word of the workspace's control block.
+int status_collect(const amber_plan_s* p, unsigned char* ws, const WsLayout& L, unsigned* dst, bool first,
+                   hipStream_t s);
 
 #define AMBER_HIP_CHECK(expr)                        \
     do {                                             \

@@ -363,7 +363,20 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     }
 }
 
+// Status bits of the last matching call into a caller's per-box word.
+__global__ void k_status_collect(const Ctrl* ctrl, unsigned* dst, int first) {
+    if (threadIdx.x == 0) dst[0] = first ? 0u : (dst[0] | ctrl->status);
+}
+
 }  // namespace
+
+int status_collect(const amber_plan_s* p, unsigned char* ws, const WsLayout& L, unsigned* dst, bool first,
+                   hipStream_t s) {
+    const Ctrl* ctrl = reinterpret_cast<const Ctrl*>(ws + L.ctrl);
+    AMBER_LAUNCH(p, "status_collect", k_status_collect, dim3(1), dim3(64), s, ctrl, dst, first ? 1 : 0);
+    AMBER_HIP_CHECK(hipGetLastError());
+    return AMBER_OK;
+}
 
 int rank_sort(const amber_plan_s* p, const float* d_J, const float* d_w, unsigned char* ws, const WsLayout& L,
               hipStream_t s, int carry, uint32_t* d_perm_out) {

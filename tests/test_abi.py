@@ -99,3 +99,17 @@ def test_package_has_no_cpu_fallback():
     src = open(os.path.join(ROOT, "paper_2109_10375_amd", "_lib.py")).read()
     assert "import oracle" not in src and "numpy" not in src
     assert "no CPU fallback" in src
+
+
+def test_batch_entry_points_check_their_arguments_on_the_host():
+    amber = _amber()
+    L = amber.lib()
+    assert "amber_batch_run" in _declared_symbols() and "amber_batch_workspace_bytes" in _declared_symbols()
+    Item = amber._lib.AmberBatchItem
+    assert L.amber_batch_workspace_bytes(None, 0) == 0
+    items = (Item * 1)()
+    assert L.amber_batch_workspace_bytes(items, 1) == 0  # no plan
+    assert L.amber_batch_run(None, 1, None, None, 0, None) == amber._lib.E_ARG
+    assert L.amber_batch_run(items, 0, None, ctypes.c_void_p(1), 1, None) == amber._lib.E_ARG
+    # an item with no plan is rejected before anything is enqueued
+    assert L.amber_batch_run(items, 1, None, ctypes.c_void_p(1), 1, None) == amber._lib.E_ARG

@@ -1,0 +1,233 @@
+"""Batches through amber_batch_run: several boxes, mean free paths and
+histories per call, HIP-graph capture and replay.
+
+Workloads:
+  * the 512^3 sweep (8 l_mfp x 4 histories on one box: one forward FFT, eight
+    multiply + inverse transforms, eight rankings, 32 inversions), in full at
+    512^3 and with the same structure at 64^3 against the FP64 oracle;
+  * the mixed batch (boxes of N in {64, 96, 128, 192, 256} with random l_mfp and
+    histories), eager and captured into a HIP graph.
+Tolerances as in the single-box tests: a batch must give bit for bit what the
+single calls give; J within relative L2 1e-5 of the oracle; z_re from an
+oracle-given intensity bit-exact; end-to-end z_re within 1e-4 per cell
+wherever FP32 J resolves the FP64 ranking (the fraction is reported and
+bounded, the ionized-mass invariant and monotonicity are checked exactly).
+"""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def amber():
+    import paper_2109_10375_amd as amber
+    assert torch.cuda.is_available()
+    amber.lib()
+    return amber
+
+
+def _hists(amber, params):
+    ors = [oracle.History.from_params(*p) for p in params]
+    return ors, [amber.History.from_coeffs(H.a, H.b, H.c) for H in ors]
+
+
+def _empty(n, k, dev):
+    return [torch.empty((n, n, n), dtype=torch.float32, device=dev) for _ in range(k)]
+
+
+def _ionized_mass_follows_history(w, z, H, zs):
+    """Sec. 3.4.2: the mass fraction with z_re > z equals x_i(z) to within one
+    cell's mass (computed on the device)."""
+    wf = w.reshape(-1).to(torch.float64)
+    tot = float(wf.sum())
+    tol = float(wf.max()) / tot + 1e-5
+    zf = z.reshape(-1)
+    for zz in zs:
+        frac = float(wf[zf > zz].sum()) / tot
+        xi = oracle.lib().oracle_weibull_x(float(zz), H.a, H.b, H.c)
+        assert abs(frac - xi) <= tol, (zz, frac, xi)
+
+
+def test_batch_equals_single_calls_and_oracle(amber):
+    dev = torch.device("cuda", 0)
+    specs = [(32, 50.0, [0.5, 3.0], [(8.0, 4.0, 3.0), (7.83, 6.54, 2.33)]),
+             (64, 100.0, [1.0, 3.0, 20.0], [(7.95, 4.68, 2.90), (8.0, 4.0, 3.0)]),
+             (96, 187.5, [5.0], [(7.91, 5.45, 2.69), (8.0, 4.0, 3.0), (7.83, 6.54, 2.33)])]
+    items, keep = [], []
+    for b, (n, L, ls, hp) in enumerate(specs):
+        cfg = inputs.BoxConfig(f"b{b}", n, L, max(2000, n ** 3 // 13), 1e9, 1e12, index=60 + b)
+        w, S = inputs.make_box(cfg)
+        ors, gh = _hists(amber, hp)
+        plan = amber.Plan(n, L)
+        J = _empty(n, len(ls), dev)
+        Z = [_empty(n, len(hp), dev) for _ in ls]
+        items.append(amber.BatchItem(plan, S.cuda(), w.cuda(), ls, J, gh, Z))
+        keep.append((cfg, w, S, ls, ors, gh, plan, J, Z))
+    # one box whose intensity is given (no radiation stage)
+    n = 64
+    Jg = inputs.make_intensity(n, 77)
+    wg = inputs.make_density(n, 78).to(torch.float32)
+    ors_g, gh_g = _hists(amber, [(8.0, 4.0, 3.0), (7.95, 4.68, 2.90)])
+    plan_g = amber.Plan(n, 1.0)
+    Zg = [_empty(n, 2, dev)]
+    items.append(amber.BatchItem(plan_g, None, wg.cuda(), [], [Jg.cuda()], gh_g, Zg))
+    batch = amber.Batch(items)
+    print("running batch of", len(items), "boxes", flush=True)
+    batch.run()
+    torch.cuda.synchronize()
+    assert batch.status.cpu().tolist() == [0] * len(items)
+
+    for cfg, w, S, ls, ors, gh, plan, J, Z in keep:
+        Js = plan.radiation(S.cuda(), ls)
+        torch.cuda.synchronize()
+        for li, l in enumerate(ls):
+            assert torch.equal(J[li], Js[li])
+            J_ref = oracle.radiation(S.numpy().astype(np.float64), cfg.box_len, l)
+            rel = np.linalg.norm(J[li].cpu().numpy() - J_ref) / np.linalg.norm(J_ref)
+            print(f"batch n={cfg.n} l={l}: J relL2={rel:.2e}", flush=True)
+            assert rel <= 1e-5
+            zs = plan.zre(Js[li], w.cuda(), gh)
+            torch.cuda.synchronize()
+            for hi in range(len(gh)):
+                assert torch.equal(Z[li][hi], zs[hi])
+    for hi, H in enumerate(ors_g):
+        z32, _ = oracle.zre(Jg.numpy(), wg.numpy(), H, mode=oracle.CONTRACT)
+        assert np.array_equal(Zg[0][hi].cpu().numpy(), z32)
+
+
+def test_sweep_structure_64_vs_oracle(amber):
+    """The 8 l_mfp x 4 histories sweep on the 64^3 box, end to end against the
+    FP64 oracle (oracle J in FP64, exact-mode inversion)."""
+    dev = torch.device("cuda", 0)
+    cfg = inputs.CONFIGS["c1"]
+    w, S = inputs.make_box(cfg)
+    ls = list(inputs.C3_LMFP)
+    ors, gh = _hists(amber, inputs.C3_HISTORIES)
+    plan = amber.Plan(cfg.n, cfg.box_len)
+    J = _empty(cfg.n, len(ls), dev)
+    Z = [_empty(cfg.n, len(gh), dev) for _ in ls]
+    batch = amber.Batch([amber.BatchItem(plan, S.cuda(), w.cuda(), ls, J, gh, Z)])
+    batch.run()
+    torch.cuda.synchronize()
+    assert batch.status.item() == 0
+    S64 = S.numpy().astype(np.float64)
+    wn = w.numpy()
+    for li, l in enumerate(ls):
+        J_ref = oracle.radiation(S64, cfg.box_len, l)
+        Jg = J[li].cpu().numpy()
+        rel = np.linalg.norm(Jg.astype(np.float64) - J_ref) / np.linalg.norm(J_ref)
+        assert rel <= 1e-5
+        pg = oracle.rank(Jg)
+        for hi, H in enumerate(ors):
+            _, z_ref = oracle.zre(J_ref, wn, H, mode=oracle.EXACT)
+            zg = Z[li][hi].cpu().numpy().astype(np.float64)
+            frac_ok = float(np.mean(np.abs(zg - z_ref) <= 1e-4))
+            print(f"sweep 64^3 l={l} hist={hi}: J relL2={rel:.2e}; z within 1e-4: {frac_ok:.5f}", flush=True)
+            # FP32 intensity resolves the FP64 ranking except among near-equal
+            # values; where the mean free path is under a cell the field is
+            # ringing-dominated and more cells swap places
+            assert frac_ok >= (0.99 if l >= 1.0 else 0.95)
+            zf = zg.reshape(-1)
+            assert np.all(np.diff(zf[pg]) <= 0)
+            _ionized_mass_follows_history(w.cuda(), Z[li][hi], H, np.linspace(H.a, 14.0, 40))
+
+
+def test_sweep_512_full(amber):
+    """The full 512^3 sweep in one batch call: sampled DFT modes of J against
+    the oracle, z_re monotone along the rank order and following the history,
+    and one (J, history) pair equal to the single call."""
+    dev = torch.device("cuda", 0)
+    cfg = inputs.CONFIGS["c3"]
+    print("generating the 512^3 box", flush=True)
+    w, S = inputs.make_box(cfg, device=dev, dtype=torch.float32)
+    ls = list(cfg.l_mfp)
+    ors, gh = _hists(amber, cfg.histories)
+    plan = amber.Plan(cfg.n, cfg.box_len)
+    J = _empty(cfg.n, len(ls), dev)
+    Z = [_empty(cfg.n, len(gh), dev) for _ in ls]
+    batch = amber.Batch([amber.BatchItem(plan, S, w, ls, J, gh, Z)])
+    batch.run()
+    torch.cuda.synchronize()
+    assert batch.status.item() == 0
+    n = cfg.n
+    Sh = S.cpu().numpy()
+    k0 = 2 * np.pi / cfg.box_len
+    modes = [(0, 0, 0), (1, 0, 0), (5, 200, 17), (256, 3, 256), (400, 100, 255)]
+    s_modes = {m: oracle.dft_coeff(Sh, m) for m in modes}
+    for li in (0, 3, 7):
+        Jh = J[li].cpu().numpy()
+        jnorm = float(np.sqrt(np.sum(Jh.astype(np.float64) ** 2)))
+        for m in modes:
+            s = [x if 2 * x <= n else x - n for x in m]
+            expect = s_modes[m] * oracle.kernel_hat(k0 * float(np.sqrt(sum(x * x for x in s))), ls[li])
+            got = oracle.dft_coeff(Jh, m)
+            assert abs(got - expect) <= 1e-5 * (abs(expect) + jnorm), (ls[li], m)
+    for li in range(len(ls)):
+        perm = plan.rank(J[li]).to(torch.int64)
+        for hi, H in enumerate(ors):
+            zp = Z[li][hi].reshape(-1)[perm]
+            assert bool((zp[1:] <= zp[:-1]).all())
+            _ionized_mass_follows_history(w, Z[li][hi], H, (H.a + 0.01, 7.0, 8.0, 9.5, 12.0))
+        del perm
+    (z1,) = plan.zre(J[3], w, [gh[2]])
+    torch.cuda.synchronize()
+    assert torch.equal(z1, Z[3][2])
+
+
+def test_mixed_batch_graph_replay(amber):
+    """Eight boxes of the mixed-size recipe, eager and as a captured HIP graph
+    replayed three times with other device work in between: every replay
+    equals the eager result bit for bit."""
+    dev = torch.device("cuda", 0)
+    cfgs = inputs.c4_boxes(8)
+    items, keep = [], []
+    for cfg in cfgs:
+        w, S = inputs.make_box(cfg, device=dev, dtype=torch.float32)
+        ors, gh = _hists(amber, cfg.histories)
+        plan = amber.Plan(cfg.n, cfg.box_len)
+        J = _empty(cfg.n, 1, dev)
+        Z = [_empty(cfg.n, 1, dev)]
+        items.append(amber.BatchItem(plan, S, w, list(cfg.l_mfp), J, gh, Z))
+        keep.append((cfg, w, S, ors, J, Z))
+    batch = amber.Batch(items)
+    print("mixed batch sizes", [c.n for c in cfgs], flush=True)
+    batch.run()
+    torch.cuda.synchronize()
+    assert batch.status.cpu().tolist() == [0] * len(items)
+    ref_J = [k[4][0].clone() for k in keep]
+    ref_Z = [k[5][0][0].clone() for k in keep]
+    for (cfg, w, S, ors, J, Z) in keep:
+        if cfg.n <= 96:
+            J_ref = oracle.radiation(S.cpu().numpy().astype(np.float64), cfg.box_len, cfg.l_mfp[0])
+            rel = np.linalg.norm(J[0].cpu().numpy() - J_ref) / np.linalg.norm(J_ref)
+            assert rel <= 1e-5
+        _ionized_mass_follows_history(w, Z[0][0], ors[0], np.linspace(ors[0].a + 0.01, 14.0, 12))
+
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            batch.run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    other = amber.Plan(64, 100.0)
+    S_other = torch.rand((64, 64, 64), device=dev)
+    for rep in range(3):
+        for (_, _, _, _, J, Z) in keep:
+            J[0].zero_()
+            Z[0][0].zero_()
+        other.radiation(S_other, [2.0 + rep])   # unrelated eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for b, (_, _, _, _, J, Z) in enumerate(keep):
+            assert torch.equal(J[0], ref_J[b]), (rep, b)
+            assert torch.equal(Z[0][0], ref_Z[b]), (rep, b)
+        assert batch.status.cpu().tolist() == [0] * len(items)
+        print(f"graph replay {rep}: equal to eager", flush=True)
