@@ -15,6 +15,7 @@ a bounded sample on this host.
 from __future__ import annotations
 
 import argparse
+import collections
 import json
 import os
 import sys
@@ -30,7 +31,13 @@ WORKLOADS = {
                             "l_mfp=3 Mpc/h, (z_mid, Delta_z, A_z)=(8, 4, 3)"),
     "c2": dict(cfg="c2", desc="single box 256^3, 500 Mpc/h, 1.3M halos on [1e10,1e12] Msun/h, "
                              "l_mfp=3 Mpc/h, (z_mid, Delta_z, A_z)=(8, 4, 3)"),
-    "c3": dict(cfg="c3", desc="single box 512^3, 1000 Mpc/h, 10M halos, l_mfp=3, (8, 4, 3)"),
+    "c3": dict(cfg="c3", desc="512^3 box, 1000 Mpc/h, 10M halos; 8 l_mfp x 4 histories in one batch call "
+                             "(1 forward FFT, 8 inverse, 8 rankings, 32 inversions)"),
+    "c4": dict(cfg=None, desc="64 boxes, N uniform in {64,96,128,192,256}, L=1.953125 N, random l_mfp and history, "
+                             "one batch call replayed as a HIP graph"),
+    "c5": dict(cfg=None, desc="Poisson requests at 20/s for 60 s, N in {128,256,512,1024} w.p. 0.4/0.3/0.2/0.1, "
+                             "l_mfp and history from the 512^3 sweep sets; resident boxes, HBM-budget admission, "
+                             "same-N batching"),
 }
 
 
@@ -144,6 +151,159 @@ def cpu_baseline(sample_n: int, min_seconds: float) -> dict:
                       f"{el:.1f} s wall"}
 
 
+def _common(args, metric: str, value: float, ms: float, desc: str, extra: dict) -> dict:
+    out = {"metric": metric, "value": value, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": {"workload": desc}}
+    out.update(extra)
+    return out
+
+
+def _time_steps(fn, steps: int, warmup: int):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        lat.append((a, b))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = sorted(x.elapsed_time(y) for x, y in lat)
+    return el, ms
+
+
+def _pct(ms, p):
+    return ms[min(len(ms) - 1, max(0, int(round(p / 100.0 * (len(ms) - 1)))))]
+
+
+def bench_sweep(args) -> dict:
+    """512^3 box, 8 l_mfp x 4 histories: one batch call per step, and the same
+    work as single calls (one radiation + one matching call per l_mfp)."""
+    import torch
+
+    import inputs
+    import paper_2109_10375_amd as amber
+
+    cfg = inputs.CONFIGS["c3"]
+    dev = torch.device("cuda", 0)
+    log(f"[bench] generating the {cfg.n}^3 box")
+    w, S = inputs.make_box(cfg, device=dev, dtype=torch.float32)
+    n, ls = cfg.n, list(cfg.l_mfp)
+    plan = amber.Plan(n, cfg.box_len)
+    hists = [amber.History.from_params(*h) for h in cfg.histories]
+    J = [torch.empty((n, n, n), dtype=torch.float32, device=dev) for _ in ls]
+    Z = [[torch.empty((n, n, n), dtype=torch.float32, device=dev) for _ in hists] for _ in ls]
+    batch = amber.Batch([amber.BatchItem(plan, S, w, ls, J, hists, Z)])
+    el, ms = _time_steps(batch.run, args.steps, args.warmup)
+    if int(batch.status.sum()) != 0:
+        raise RuntimeError("device status set")
+
+    def serial():
+        for li, l in enumerate(ls):
+            plan.radiation(S, [l], out=[J[li]])
+            plan.zre(J[li], w, hists, out=Z[li])
+
+    el_s, ms_s = _time_steps(serial, args.steps, args.warmup)
+    fields = args.steps * n ** 3 * len(ls)
+    return _common(args, "J fields x cells/s (8 l_mfp x 4 histories per 512^3 box)", fields / el,
+                   1e3 * el / args.steps, WORKLOADS["c3"]["desc"],
+                   {"p50_ms": round(_pct(ms, 50), 3), "p99_ms": round(_pct(ms, 99), 3),
+                    "serial_single_calls": {"value": fields / el_s, "ms_per_step": 1e3 * el_s / args.steps,
+                                            "p50_ms": round(_pct(ms_s, 50), 3)},
+                    "zre_fields_per_step": len(ls) * len(hists)})
+
+
+def bench_mixed(args) -> dict:
+    """64 boxes of mixed size in one batch, eager and as a replayed HIP graph,
+    next to the same boxes as single calls."""
+    import torch
+
+    import inputs
+    import paper_2109_10375_amd as amber
+
+    dev = torch.device("cuda", 0)
+    cfgs = inputs.c4_boxes(64)
+    items, singles = [], []
+    log(f"[bench] generating {len(cfgs)} boxes")
+    for cfg in cfgs:
+        w, S = inputs.make_box(cfg, device=dev, dtype=torch.float32)
+        n = cfg.n
+        plan = amber.Plan(n, cfg.box_len)
+        h = amber.History.from_params(*cfg.histories[0])
+        J = torch.empty((n, n, n), dtype=torch.float32, device=dev)
+        z = torch.empty_like(J)
+        items.append(amber.BatchItem(plan, S, w, list(cfg.l_mfp), [J], [h], [[z]]))
+        singles.append((plan, S, w, cfg.l_mfp[0], J, h, z))
+    batch = amber.Batch(items)
+    cells = sum(c.n ** 3 for c in cfgs)
+    el_e, ms_e = _time_steps(batch.run, args.steps, args.warmup)
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            batch.run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    el_g, ms_g = _time_steps(g.replay, args.steps, args.warmup)
+    if int(batch.status.sum()) != 0:
+        raise RuntimeError("device status set")
+
+    def serial():
+        for plan, S, w, l, J, h, z in singles:
+            plan.radiation(S, [l], out=[J])
+            plan.zre(J, w, [h], out=[z])
+
+    el_s, ms_s = _time_steps(serial, args.steps, args.warmup)
+    return _common(args, "grid cells/s over a mixed batch of 64 boxes (HIP graph replay)",
+                   args.steps * cells / el_g, 1e3 * el_g / args.steps, WORKLOADS["c4"]["desc"],
+                   {"cells_per_step": cells, "sizes": sorted(collections.Counter(c.n for c in cfgs).items()),
+                    "p50_ms": round(_pct(ms_g, 50), 3), "p99_ms": round(_pct(ms_g, 99), 3),
+                    "eager_batch": {"value": args.steps * cells / el_e, "ms_per_step": 1e3 * el_e / args.steps},
+                    "serial_single_calls": {"value": args.steps * cells / el_s,
+                                            "ms_per_step": 1e3 * el_s / args.steps}})
+
+
+def bench_serving(args) -> dict:
+    """Poisson request stream served from resident boxes."""
+    import torch
+
+    import inputs
+    import paper_2109_10375_amd as amber
+    from paper_2109_10375_amd import serve
+
+    dev = torch.device("cuda", 0)
+    boxes = {}
+    for n in (128, 256, 512, 1024):
+        cfg = inputs.BoxConfig(f"c5.{n}", n, 1.953125 * n, max(1000, int(1.3e6 * (n / 256) ** 3)), 1e10, 1e12,
+                               index=200 + n)
+        log(f"[bench] generating the resident {n}^3 box")
+        w, S = inputs.make_box(cfg, device=dev, dtype=torch.float32)
+        boxes[n] = serve.Box(amber.Plan(n, cfg.box_len), S, w)
+    server = serve.Server(boxes, hbm_budget_bytes=args.hbm_budget_gb * 2 ** 30, max_batch=16)
+    warm = serve.requests_from(inputs.c5_requests(2.0, seed=55))
+    server.serve(warm)
+    reqs = serve.requests_from(inputs.c5_requests(args.serve_seconds))
+    offered = sum(r.n ** 3 for r in reqs) / args.serve_seconds
+    log(f"[bench] serving {len(reqs)} requests ({offered / 1e9:.2f} G cells/s offered)")
+    st = server.serve(reqs)
+    return _common(args, "served grid cells/s (Poisson requests, p50/p99 latency)", st["cells_per_s_busy"],
+                   1e3 * st["busy_s"] / max(1, st["batches"]), WORKLOADS["c5"]["desc"],
+                   {"p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                    "mean_latency_ms": round(st["mean_ms"], 3), "requests": st["requests"],
+                    "batches": st["batches"], "offered_cells_per_s": offered,
+                    "makespan_s": round(st["makespan_s"], 3), "busy_s": round(st["busy_s"], 3),
+                    "hbm_budget_gb": args.hbm_budget_gb, "arrivals_s": args.serve_seconds})
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +313,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=128)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="c5: seconds of Poisson arrivals")
+    ap.add_argument("--hbm-budget-gb", type=int, default=96, help="c5: HBM for outputs of requests in flight")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain copy of MIB MiB (for HBM counter calibration)")
     args = ap.parse_args()
@@ -168,6 +330,11 @@ def main() -> int:
     import paper_2109_10375_amd as amber
 
     amber.lib()  # raises when the HIP library is missing: there is no fallback
+    if args.workload in ("c3", "c4", "c5"):
+        torch.cuda.set_device(0)
+        out = {"c3": bench_sweep, "c4": bench_mixed, "c5": bench_serving}[args.workload](args)
+        print(json.dumps(out), flush=True)
+        return 0
     wl = WORKLOADS[args.workload]
     cfg = inputs.CONFIGS[wl["cfg"]]
     n, n3 = cfg.n, cfg.n ** 3

@@ -263,15 +263,22 @@ class BatchItem:
 class Batch:
     """A fixed list of boxes run by amber_batch_run with one shared workspace."""
 
-    def __init__(self, items: Sequence[BatchItem]):
+    def __init__(self, items: Sequence[BatchItem], ws: torch.Tensor | None = None):
         self.items = list(items)
         self._arr = (AmberBatchItem * len(self.items))(*[it.c for it in self.items])
         need = int(lib().amber_batch_workspace_bytes(self._arr, len(self.items)))
         if need == 0:
             raise ValueError("invalid batch")
         self.device = self.items[0].plan.device
-        self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        if ws is not None and (not ws.is_cuda or ws.dtype != torch.uint8 or ws.numel() < need):
+            raise ValueError(f"workspace: expected a CUDA uint8 tensor of at least {need} bytes")
+        self.ws = ws if ws is not None else torch.empty(need, dtype=torch.uint8, device=self.device)
         self.status = torch.zeros(len(self.items), dtype=torch.int32, device=self.device)
+
+    @staticmethod
+    def workspace_bytes(items: Sequence[BatchItem]) -> int:
+        arr = (AmberBatchItem * len(items))(*[it.c for it in items])
+        return int(lib().amber_batch_workspace_bytes(arr, len(items)))
 
     def run(self) -> None:
         """amber_batch_run on torch's current stream; per-box status bits land in self.status."""
