@@ -227,7 +227,7 @@ struct Acc<true> {
 };
 
 // Exact mass of every tile, before any rank is matched: block g sums tiles
-// kTilesPerBlock g .. kTilesPerBlock (g + 1) - 1 of the sorted weights and
+// tpb g .. tpb (g + 1) - 1 of the sorted weights (tpb <= kTilesPerBlock) and
 // keeps, per tile, the exclusive prefix within the block (local[tile]) and the
 // block's total.  Every weight is also checked: its scaled value m 2^(q - qmin)
 // must fit in 127 bits, and so must every partial sum.
@@ -241,7 +241,7 @@ __device__ __forceinline__ u128 add128_checked(u128 a, u128 b, bool& bad) {
 
 __global__ __launch_bounds__(kScanThreads) void k_tile_sums(const float* __restrict__ w_sorted, long long n, Ctrl* ctrl,
                                                         u128* __restrict__ local, u128* __restrict__ block_tot,
-                                                        long long n_tiles) {
+                                                        long long n_tiles, int tpb) {
     __shared__ u128 s_wave[kTilesPerBlock][kScanWaves];
     __shared__ u128 s_tile[kTilesPerBlock];
     __shared__ int s_bad;
@@ -251,8 +251,8 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_sums(const float* __restr
     bool bad = false;
     // no barrier inside the loop: each wave keeps its sum per tile
 #pragma unroll 2
-    for (int k = 0; k < kTilesPerBlock; ++k) {
-        const long long tile = (long long)blockIdx.x * kTilesPerBlock + k;
+    for (int k = 0; k < tpb; ++k) {
+        const long long tile = (long long)blockIdx.x * tpb + k;
         const long long p0 = tile * kScanTile + (long long)tid * kPer;
         u128 sum = {0ull, 0ull};
         if (tile < n_tiles && p0 < n) {
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_sums(const float* __restr
     }
     if (bad) s_bad = 1;
     __syncthreads();
-    if (tid < kTilesPerBlock) {
+    if (tid < tpb) {
         u128 t = {0ull, 0ull};
         bool b2 = false;
         for (int w = 0; w < kScanWaves; ++w) t = add128_checked(t, s_wave[tid][w], b2);
@@ -296,8 +296,8 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_sums(const float* __restr
     if (tid == 0) {
         u128 running = {0ull, 0ull};
         bool b3 = false;
-        for (int k = 0; k < kTilesPerBlock; ++k) {
-            const long long tile = (long long)blockIdx.x * kTilesPerBlock + k;
+        for (int k = 0; k < tpb; ++k) {
+            const long long tile = (long long)blockIdx.x * tpb + k;
             if (tile < n_tiles) local[tile] = running;
             running = add128_checked(running, s_tile[k], b3);
         }
@@ -306,40 +306,50 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_sums(const float* __restr
     }
 }
 
-// Exclusive prefix of the block totals (one block of 1024 threads), the exact
-// grand total C_N, and whether it needs more than 64 bits.
+// Exclusive prefix of the block totals (one block of 1024 threads: a serial
+// sum over each thread's chunk, a block-wide scan of the chunk sums, a serial
+// pass writing the prefixes), the exact grand total C_N, and whether it needs
+// more than 64 bits.
 constexpr int kPrefixThreads = 1024;
 __global__ __launch_bounds__(kPrefixThreads) void k_block_prefix(u128* __restrict__ block_tot, long long nb,
                                                                  Ctrl* ctrl) {
-    __shared__ u128 s_part[kPrefixThreads];
-    const int tid = threadIdx.x;
+    __shared__ u128 s_wave[kPrefixThreads / 64];
+    __shared__ int s_bad;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) s_bad = 0;
     const long long per = (nb + kPrefixThreads - 1) / kPrefixThreads;
     const long long b0 = (long long)tid * per;
     u128 sum = {0ull, 0ull};
     bool bad = false;
     for (long long b = b0; b < b0 + per && b < nb; ++b) sum = add128_checked(sum, block_tot[b], bad);
-    s_part[tid] = sum;
-    __syncthreads();
-    if (tid == 0) {
-        u128 run = {0ull, 0ull};
-        for (int i = 0; i < kPrefixThreads; ++i) {
-            const u128 v = s_part[i];
-            s_part[i] = run;
-            run = add128_checked(run, v, bad);
-        }
-        ctrl->total_lo = run.lo;
-        ctrl->total_hi = run.hi;
-        ctrl->wide = run.hi != 0ull;
-        if (bad || (run.hi >> 63)) atomicOr(&ctrl->status, AMBER_STATUS_RANGE);
+    // inclusive scan over the wave, then over the waves
+    u128 inc = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const u128 o = shfl_up128(inc, d);
+        if (lane >= d) inc = add128_checked(inc, o, bad);
     }
+    if (lane == 63) s_wave[wave] = inc;
     __syncthreads();
-    u128 run = s_part[tid];
+    u128 wave_excl = {0ull, 0ull};
+    for (int w = 0; w < wave; ++w) wave_excl = add128_checked(wave_excl, s_wave[w], bad);
+    u128 total = {0ull, 0ull};
+    if (tid == kPrefixThreads - 1) total = add128_checked(wave_excl, inc, bad);
+    u128 run = add128(wave_excl, inc);
+    run = u128{run.lo - sum.lo, run.hi - sum.hi - (run.lo < sum.lo ? 1ull : 0ull)};  // exclusive
     for (long long b = b0; b < b0 + per && b < nb; ++b) {
         const u128 v = block_tot[b];
         block_tot[b] = run;
         run = add128(run, v);
     }
-    if (bad) atomicOr(&ctrl->status, AMBER_STATUS_RANGE);
+    if (bad) s_bad = 1;
+    __syncthreads();
+    if (tid == kPrefixThreads - 1) {
+        ctrl->total_lo = total.lo;
+        ctrl->total_hi = total.hi;
+        ctrl->wide = total.hi != 0ull;
+        if (s_bad || (total.hi >> 63)) atomicOr(&ctrl->status, AMBER_STATUS_RANGE);
+    }
 }
 
 // One block per tile of kScanTile consecutive ranks; thread t owns ranks
@@ -363,7 +373,7 @@ template <int NH, bool WIDE>
 __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
     const unsigned* __restrict__ perm, const float* __restrict__ w_sorted, long long n, Ctrl* ctrl,
     const u128* __restrict__ local, const u128* __restrict__ block_excl, unsigned* __restrict__ fill,
-    unsigned bucket_size, double bucket_rinv, HistArgs hs, unsigned* __restrict__ part_idx,
+    int tpb, unsigned bucket_size, double bucket_rinv, HistArgs hs, unsigned* __restrict__ part_idx,
     float* __restrict__ part_z0, float* __restrict__ part_z1, float* __restrict__ part_z2) {
     using A = Acc<WIDE>;
     if ((ctrl->wide != 0) != WIDE) return;
@@ -437,7 +447,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
     }
     __syncthreads();  // every bucket's loff and gbase are read below
 
-    const u128 tile_excl = add128(block_excl[tile / kTilesPerBlock], local[tile]);
+    const u128 tile_excl = add128(block_excl[tile / tpb], local[tile]);
     A run = A::of128(tile_excl) + wave_excl + thread_excl;
     const u128 total = {ctrl->total_lo, ctrl->total_hi};
     const double tot = u128_to_f64(total);
@@ -638,9 +648,10 @@ __global__ __launch_bounds__(kPartThreads) void k_partition2(const unsigned* __r
         if (dst[kk] != 0xffffffffu) out_z[dst[kk]] = __uint_as_float(stage[tid + kk * kPartThreads]);
 }
 
-// Last level: block L owns cells [L S, (L+1) S) (S <= 16384) and exactly the
-// pairs at positions [L S, (L+1) S); it places z by cell in LDS and writes the
-// run of z_re contiguously.
+// Last level: block L owns cells [L S, (L+1) S) (S <= 16384, a whole number of
+// the previous level's ranges, whose pairs sit at exactly the positions of
+// their cells) and the pairs at positions [L S, (L+1) S); it places z by cell
+// in LDS and writes the run of z_re contiguously.
 constexpr int kLeafMax = 16384;
 constexpr int kLeafThreads = 1024;
 __global__ __launch_bounds__(kLeafThreads) void k_leaf_scatter(const unsigned* __restrict__ in_idx,
@@ -649,13 +660,15 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_scatter(const unsigned* _
     constexpr int kR = kLeafMax / kLeafThreads;
     __shared__ float zl[kLeafMax];
     const long long start = (long long)blockIdx.x * S;
+    const long long left = n - start;
+    const unsigned valid = left < (long long)S ? (unsigned)left : S;
     unsigned c[kR];
     float z[kR];
     // every load in flight before any is used (clamped positions, no branch)
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const unsigned i = threadIdx.x + r * kLeafThreads;
-        const long long at = start + (i < S ? i : 0u);
+        const long long at = start + (i < valid ? i : 0u);
         c[r] = in_idx[at];
         z[r] = in_z[at];
     }
@@ -663,13 +676,13 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_scatter(const unsigned* _
     for (int r = 0; r < kR; ++r) {
         const unsigned i = threadIdx.x + r * kLeafThreads;
         const long long rel = (long long)c[r] - start;
-        if (i < S && rel >= 0 && rel < (long long)S) zl[rel] = z[r];
+        if (i < valid && rel >= 0 && rel < (long long)valid) zl[rel] = z[r];
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const unsigned i = threadIdx.x + r * kLeafThreads;
-        if (i < S) out[start + i] = zl[i];
+        if (i < valid) out[start + i] = zl[i];
     }
 }
 
@@ -684,7 +697,10 @@ int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, flo
                const WsLayout& L, hipStream_t s) {
     const long long n = (long long)p->n * p->n * p->n;
     const long long n_tiles = (n + kScanTile - 1) / kScanTile;
-    const long long n_blocks = (n_tiles + kTilesPerBlock - 1) / kTilesPerBlock;
+    // tiles per tile-sum block: up to kTilesPerBlock, fewer when that would
+    // leave the device short of blocks
+    const int sum_tpb = (int)std::max(1LL, std::min((long long)kTilesPerBlock, n_tiles / 1024));
+    const long long n_blocks = (n_tiles + sum_tpb - 1) / sum_tpb;
     const long long lbw = lb_words(n);  // words per look-back region
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
     const unsigned* perm = reinterpret_cast<const unsigned*>(ws + L.vals[0]);
@@ -708,10 +724,13 @@ int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, flo
     const unsigned S2 = two_level ? S1 / kL2 : S1;  // divides exactly for the supported sizes
     const unsigned tpb = (S1 + kPartTile - 1) / kPartTile;
     const double s2_rinv = 1.0 / (double)S2;
+    // leaf blocks take whole ranges of the last level, up to kLeafMax cells
+    const unsigned leaf = S2 * (unsigned)(kLeafMax / S2);
+    const unsigned leaf_blocks = (unsigned)((n + leaf - 1) / leaf);
     const dim3 grid((unsigned)n_tiles), blk(kScanThreads);
 
     AMBER_LAUNCH(p, "match_tile_sums", k_tile_sums, dim3((unsigned)n_blocks), blk, s, w_sorted, n, ctrl, local,
-                 block_excl, n_tiles);
+                 block_excl, n_tiles, sum_tpb);
     AMBER_LAUNCH(p, "match_block_prefix", k_block_prefix, dim3(1), dim3(kPrefixThreads), s, block_excl, n_blocks, ctrl);
     const double rinv = 1.0 / (double)S1;
     for (int g = 0; g * kGroup < n_hist; ++g) {
@@ -726,9 +745,9 @@ int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, flo
         if (g > 0) AMBER_LAUNCH(p, "match_clear", k_clear, dim3(1), dim3(256), s, fill1, kL1);
 #define AMBER_SCAN(NHV)                                                                                      \
     AMBER_LAUNCH(p, "match_scan_partition", (k_scan_partition<NHV, false>), grid, blk, s, perm, w_sorted, n, \
-                 ctrl, local, block_excl, fill1, S1, rinv, hs, p1_idx, p1_z[0], p1_z[1], p1_z[2]);           \
+                 ctrl, local, block_excl, fill1, sum_tpb, S1, rinv, hs, p1_idx, p1_z[0], p1_z[1], p1_z[2]);  \
     AMBER_LAUNCH(p, "match_scan_partition_wide", (k_scan_partition<NHV, true>), grid, blk, s, perm, w_sorted, \
-                 n, ctrl, local, block_excl, fill1, S1, rinv, hs, p1_idx, p1_z[0], p1_z[1], p1_z[2]);
+                 n, ctrl, local, block_excl, fill1, sum_tpb, S1, rinv, hs, p1_idx, p1_z[0], p1_z[1], p1_z[2]);
         switch (hs.n) {
             case 1: AMBER_SCAN(1) break;
             case 2: AMBER_SCAN(2) break;
@@ -740,11 +759,11 @@ int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, flo
                 AMBER_LAUNCH(p, "match_clear", k_clear, dim3(256), dim3(256), s, fill2, 65536);
                 AMBER_LAUNCH(p, "match_partition2", k_partition2, dim3(kL1 * tpb), dim3(kPartThreads), s, p1_idx, p1_z[i], n, fill2,
                              S1, S2, s2_rinv, tpb, p2_idx, p2_z);
-                AMBER_LAUNCH(p, "match_leaf_scatter", k_leaf_scatter, dim3((unsigned)(n / S2)), dim3(kLeafThreads), s,
-                             p2_idx, p2_z, n, S2, d_zre[h0 + i]);
+                AMBER_LAUNCH(p, "match_leaf_scatter", k_leaf_scatter, dim3(leaf_blocks), dim3(kLeafThreads), s,
+                             p2_idx, p2_z, n, leaf, d_zre[h0 + i]);
             } else {
-                AMBER_LAUNCH(p, "match_leaf_scatter", k_leaf_scatter, dim3(kL1), dim3(kLeafThreads), s, p1_idx,
-                             p1_z[i], n, S1, d_zre[h0 + i]);
+                AMBER_LAUNCH(p, "match_leaf_scatter", k_leaf_scatter, dim3(leaf_blocks), dim3(kLeafThreads), s,
+                             p1_idx, p1_z[i], n, leaf, d_zre[h0 + i]);
             }
         }
     }

@@ -6,9 +6,8 @@
 // of the intensity (-0 folded onto +0).  The input is read in cell-index order
 // and every pass is stable, so equal intensities keep ascending cell index.
 //
-// Each pass ("onesweep"): a block takes the next tile (16384 keys; long digit
-// runs keep the scattered writes close to whole cache lines) from a ticket
-// counter, ranks its keys by digit with 64-lane ballots (the lanes that share a
+// Each pass ("onesweep"): a block takes the next tile (16384 keys on large
+// grids, 4096 on small ones) from a ticket counter, ranks its keys by digit with 64-lane ballots (the lanes that share a
 // digit find each other with 8 ballots; the lowest of them bumps the wave's LDS
 // counter), publishes its per-digit counts for later tiles and looks back over
 // earlier tiles' published counts (decoupled look-back) to find where its
@@ -23,14 +22,12 @@ namespace {
 
 constexpr int kHistThreads = 256;
 constexpr int kHistWaves = kHistThreads / 64;
-#ifndef AMBER_SORT_THREADS
-#define AMBER_SORT_THREADS 1024
-#endif
-constexpr int kThreads = AMBER_SORT_THREADS;  // one onesweep tile per block
-constexpr int kWaves = kThreads / 64;
 constexpr int kKeysPerThread = 16;
-constexpr int kTile = kThreads * kKeysPerThread;
-static_assert(kThreads >= 256 && kThreads % 64 == 0 && kTile <= 65535, "tile geometry");
+// One onesweep tile per block: 16384 keys (1024 threads) on large grids, where
+// long digit runs keep the scattered writes close to whole cache lines; 4096
+// keys (256 threads) below 2^24 keys, where more tiles keep more CUs busy.
+constexpr int kBigThreads = 1024, kSmallThreads = 256;
+constexpr long long kBigTileFrom = 1LL << 24;
 constexpr unsigned kFlagAgg = 1u << 30;
 constexpr unsigned kFlagPre = 2u << 30;
 
@@ -174,16 +171,19 @@ __global__ __launch_bounds__(1024) void k_qmin(const int* __restrict__ qtile, lo
     }
 }
 
-// One digit pass over tiles of kTile keys.  FIRST: keys come from J and the
-// index is the position.  LAST: only the values (and weights) are written.
-// CARRY: weights travel with the keys; pass 0 also checks them and stores the
-// smallest ulp exponent of each tile in qtile[tile].
-template <bool FIRST, bool LAST, bool CARRY>
+// One digit pass over tiles of kThreads * kKeysPerThread keys.  FIRST: keys
+// come from J and the index is the position.  LAST: only the values (and
+// weights) are written.  CARRY: weights travel with the keys; pass 0 also
+// checks them and stores the smallest ulp exponent of each tile in qtile[tile].
+template <int kThreads, bool FIRST, bool LAST, bool CARRY>
 __global__ __launch_bounds__(kThreads) void k_onesweep(
     const float* __restrict__ J, const unsigned* __restrict__ keys_in, const unsigned* __restrict__ vals_in,
     const float* __restrict__ w_in, unsigned* __restrict__ keys_out, unsigned* __restrict__ vals_out,
     float* __restrict__ w_out, unsigned* __restrict__ lb, unsigned* __restrict__ lb_next,
     unsigned* __restrict__ lb_next2, int* __restrict__ qtile, Ctrl* ctrl, int pass, long long n) {
+    constexpr int kWaves = kThreads / 64;
+    constexpr int kTile = kThreads * kKeysPerThread;
+    static_assert(kThreads >= 256 && kThreads % 64 == 0 && kTile <= 65535, "tile geometry");
     __shared__ unsigned s_tile;
     __shared__ unsigned short wcnt[kWaves][256];  // per-wave digit counts, then wave offsets
     __shared__ unsigned loff[256];                // tile-local start of each digit
@@ -378,10 +378,40 @@ int status_collect(const amber_plan_s* p, unsigned char* ws, const WsLayout& L, 
     return AMBER_OK;
 }
 
+template <int T>
+static void launch_passes(const amber_plan_s* p, const float* d_J, const float* d_w, hipStream_t s, int carry,
+                          unsigned* const* keys, unsigned* const* vals, float* const* wts, unsigned* const* lb,
+                          uint32_t* final_vals, int* qtile, Ctrl* ctrl, long long n, long long n_tiles) {
+    const dim3 grid((unsigned)n_tiles), blk(T);
+    // pass 0: J, w -> buffers 1; pass 1: 1 -> 0; pass 2: 0 -> 1; pass 3: 1 -> 0 (values, weights)
+    if (carry) {
+        AMBER_LAUNCH(p, "rank_pass0", (k_onesweep<T, true, false, true>), grid, blk, s, d_J, nullptr, nullptr, d_w,
+                     keys[1], vals[1], wts[1], lb[0], lb[1], nullptr, qtile, ctrl, 0, n);
+        AMBER_LAUNCH(p, "rank_qmin", k_qmin, dim3(1), dim3(1024), s, qtile, n_tiles, ctrl);
+        AMBER_LAUNCH(p, "rank_pass1", (k_onesweep<T, false, false, true>), grid, blk, s, nullptr, keys[1], vals[1],
+                     wts[1], keys[0], vals[0], wts[0], lb[1], lb[0], nullptr, nullptr, ctrl, 1, n);
+        AMBER_LAUNCH(p, "rank_pass2", (k_onesweep<T, false, false, true>), grid, blk, s, nullptr, keys[0], vals[0],
+                     wts[0], keys[1], vals[1], wts[1], lb[0], lb[1], nullptr, nullptr, ctrl, 2, n);
+        AMBER_LAUNCH(p, "rank_pass3", (k_onesweep<T, false, true, true>), grid, blk, s, nullptr, keys[1], vals[1],
+                     wts[1], nullptr, final_vals, wts[0], lb[1], lb[0], lb[2], nullptr, ctrl, 3, n);
+    } else {
+        AMBER_LAUNCH(p, "rank_pass0", (k_onesweep<T, true, false, false>), grid, blk, s, d_J, nullptr, nullptr,
+                     nullptr, keys[1], vals[1], nullptr, lb[0], lb[1], nullptr, nullptr, ctrl, 0, n);
+        AMBER_LAUNCH(p, "rank_pass1", (k_onesweep<T, false, false, false>), grid, blk, s, nullptr, keys[1], vals[1],
+                     nullptr, keys[0], vals[0], nullptr, lb[1], lb[0], nullptr, nullptr, ctrl, 1, n);
+        AMBER_LAUNCH(p, "rank_pass2", (k_onesweep<T, false, false, false>), grid, blk, s, nullptr, keys[0], vals[0],
+                     nullptr, keys[1], vals[1], nullptr, lb[0], lb[1], nullptr, nullptr, ctrl, 2, n);
+        AMBER_LAUNCH(p, "rank_pass3", (k_onesweep<T, false, true, false>), grid, blk, s, nullptr, keys[1], vals[1],
+                     nullptr, nullptr, final_vals, nullptr, lb[1], lb[0], lb[2], nullptr, ctrl, 3, n);
+    }
+}
+
 int rank_sort(const amber_plan_s* p, const float* d_J, const float* d_w, unsigned char* ws, const WsLayout& L,
               hipStream_t s, int carry, uint32_t* d_perm_out) {
     const long long n = (long long)p->n * p->n * p->n;
-    const long long n_tiles = (n + kTile - 1) / kTile;
+    const bool big = n >= kBigTileFrom;
+    const long long tile = (long long)(big ? kBigThreads : kSmallThreads) * kKeysPerThread;
+    const long long n_tiles = (n + tile - 1) / tile;
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
     unsigned* keys[2] = {reinterpret_cast<unsigned*>(ws + L.keys[0]), reinterpret_cast<unsigned*>(ws + L.keys[1])};
     unsigned* vals[2] = {reinterpret_cast<unsigned*>(ws + L.vals[0]), reinterpret_cast<unsigned*>(ws + L.vals[1])};
@@ -396,32 +426,14 @@ int rank_sort(const amber_plan_s* p, const float* d_J, const float* d_w, unsigne
         (unsigned)std::min<long long>(2048, (n + kHistThreads * 16 - 1) / (kHistThreads * 16));
     AMBER_LAUNCH(p, "rank_hist", k_hist, dim3(hist_blocks), dim3(kHistThreads), s, d_J, n, ctrl, lb[0], n_tiles * 256);
     AMBER_LAUNCH(p, "rank_digit_offsets", k_digit_offsets, dim3(1), dim3(256), s, ctrl);
-    const dim3 grid((unsigned)n_tiles), blk(kThreads);
-    // pass 0: J, w -> buffers 1; pass 1: 1 -> 0; pass 2: 0 -> 1; pass 3: 1 -> 0 (values, weights)
     uint32_t* final_vals = d_perm_out ? d_perm_out : vals[0];
     // the per-tile ulp exponents of pass 0 live in the third look-back region
     // until the last pass clears it
     int* qtile = reinterpret_cast<int*>(lb[2]);
-    if (carry) {
-        AMBER_LAUNCH(p, "rank_pass0", (k_onesweep<true, false, true>), grid, blk, s, d_J, nullptr, nullptr, d_w, keys[1],
-                     vals[1], wts[1], lb[0], lb[1], nullptr, qtile, ctrl, 0, n);
-        AMBER_LAUNCH(p, "rank_qmin", k_qmin, dim3(1), dim3(1024), s, qtile, n_tiles, ctrl);
-        AMBER_LAUNCH(p, "rank_pass1", (k_onesweep<false, false, true>), grid, blk, s, nullptr, keys[1], vals[1], wts[1],
-                     keys[0], vals[0], wts[0], lb[1], lb[0], nullptr, nullptr, ctrl, 1, n);
-        AMBER_LAUNCH(p, "rank_pass2", (k_onesweep<false, false, true>), grid, blk, s, nullptr, keys[0], vals[0], wts[0],
-                     keys[1], vals[1], wts[1], lb[0], lb[1], nullptr, nullptr, ctrl, 2, n);
-        AMBER_LAUNCH(p, "rank_pass3", (k_onesweep<false, true, true>), grid, blk, s, nullptr, keys[1], vals[1], wts[1],
-                     nullptr, final_vals, wts[0], lb[1], lb[0], lb[2], nullptr, ctrl, 3, n);
-    } else {
-        AMBER_LAUNCH(p, "rank_pass0", (k_onesweep<true, false, false>), grid, blk, s, d_J, nullptr, nullptr, nullptr,
-                     keys[1], vals[1], nullptr, lb[0], lb[1], nullptr, nullptr, ctrl, 0, n);
-        AMBER_LAUNCH(p, "rank_pass1", (k_onesweep<false, false, false>), grid, blk, s, nullptr, keys[1], vals[1],
-                     nullptr, keys[0], vals[0], nullptr, lb[1], lb[0], nullptr, nullptr, ctrl, 1, n);
-        AMBER_LAUNCH(p, "rank_pass2", (k_onesweep<false, false, false>), grid, blk, s, nullptr, keys[0], vals[0],
-                     nullptr, keys[1], vals[1], nullptr, lb[0], lb[1], nullptr, nullptr, ctrl, 2, n);
-        AMBER_LAUNCH(p, "rank_pass3", (k_onesweep<false, true, false>), grid, blk, s, nullptr, keys[1], vals[1],
-                     nullptr, nullptr, final_vals, nullptr, lb[1], lb[0], lb[2], nullptr, ctrl, 3, n);
-    }
+    if (big)
+        launch_passes<kBigThreads>(p, d_J, d_w, s, carry, keys, vals, wts, lb, final_vals, qtile, ctrl, n, n_tiles);
+    else
+        launch_passes<kSmallThreads>(p, d_J, d_w, s, carry, keys, vals, wts, lb, final_vals, qtile, ctrl, n, n_tiles);
     AMBER_HIP_CHECK(hipGetLastError());
     return AMBER_OK;
 }
