@@ -108,6 +108,27 @@ def measured_traffic(name: str, n: int) -> tuple[float | None, str]:
     return None, "no counter entry for this kernel"
 
 
+def copy_peak_gbs(gib: int = 4, reps: int = 10) -> float:
+    """Read + write bandwidth of a plain elementwise copy (torch.neg) of
+    ``gib`` GiB: the practical HBM ceiling the kernels are compared with."""
+    import torch
+
+    x = torch.ones(gib * 2 ** 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(2):
+        torch.neg(x, out=y)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        torch.neg(x, out=y)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * gib * 2 ** 30 / (ms * 1e-3) / 1e9
+
+
 def copy_calibration(mib: int) -> None:
     """A plain elementwise copy (negation) of `mib` MiB, three times: the known
     byte count against which the HBM counters are calibrated."""
@@ -144,7 +165,15 @@ def cpu_baseline(sample_n: int, min_seconds: float) -> dict:
         el = time.perf_counter() - t0
         if el >= min_seconds:
             break
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": boxes * sample_n ** 3 / el, "unit": "cells/s", "cores": oracle.num_threads(),
+            "host": {"nproc": os.cpu_count(), "cpu": model, "omp_threads": oracle.num_threads(),
+                     "note": "the radiation DFT loops use every thread; the rank order is one qsort"},
             "kind": "oracle",
             "sample": f"{boxes} box(es) of {sample_n}^3 (L={cfg.box_len:g} Mpc/h, l_mfp=3, (8,4,3)), "
                       f"FP64 naive-DFT radiation + qsort rank + exact-mass contract-mode matching, "
@@ -389,6 +418,7 @@ def main() -> int:
         i = min(len(lat) - 1, max(0, int(round(p / 100.0 * (len(lat) - 1)))))
         return lat[i]
 
+    copy_gbs = copy_peak_gbs()
     alg = algorithmic_bytes(n)
     rows = []
     for name, (launches, tot_ms) in prof.items():
@@ -428,6 +458,12 @@ def main() -> int:
         "p99_ms": round(pct(99), 3),
         "pipeline_alg_bytes_per_step": pipe_bytes,
         "pipeline_frac_hbm": round(pipe_bytes / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+        # the fixed pass model of the pipeline (FFT 40 + sort 60 + scan 12 bytes per cell) and the
+        # compulsory I/O (S, J twice, w, z: 20 bytes per cell), against the spec and a measured copy
+        "pass_model_frac_hbm": round(112 * n3 / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+        "compulsory_io_frac_hbm": round(20 * n3 / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+        "copy_peak_gbs": round(copy_gbs, 1),
+        "pass_model_frac_copy": round(112 * n3 / (elapsed / args.steps) / 1e9 / copy_gbs, 4),
         "roofline": roof,
         "kernels_ms_per_step": {r[1]: round(r[0] / args.steps, 4) for r in rows},
     }
