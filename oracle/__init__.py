@@ -69,6 +69,7 @@ def lib():
         L.oracle_kernel_real.argtypes = [i, d, d, p]
         L.oracle_direct_convolution.argtypes = [i, d, p, d, p]
         L.oracle_dft_coeff_f32.argtypes = [i, p, i, i, i, pd, pd]
+        L.oracle_spectra.argtypes = [i, d, p, i, p, i, i, p, p, p, p, p]
         L.oracle_rank_f32.argtypes = [i64, p, p]
         L.oracle_rank_f64.argtypes = [i64, p, p]
         L.oracle_mass_fraction.argtypes = [i64, p, p, p]
@@ -214,6 +215,27 @@ def dft_coeff(field: np.ndarray, m: tuple[int, int, int]) -> complex:
     _check(lib().oracle_dft_coeff_f32(f.shape[0], _ptr(f), int(m[0]), int(m[1]), int(m[2]),
                                       ctypes.byref(re), ctypes.byref(im)), "dft_coeff")
     return complex(re.value, im.value)
+
+
+FIELD_RAW, FIELD_OVERDENSITY, FIELD_REDSHIFT = 0, 1, 2
+
+
+def spectra(a: np.ndarray, b: np.ndarray | None, box_len: float, n_bins: int, kind_a: int = FIELD_RAW,
+            kind_b: int | None = None) -> dict:
+    """Shell-averaged auto and cross power spectra (Sec. 2.3, Eqs. Pk, Dk,
+    bias, rcc; readings D1, D2), with Delta^2, b_ab and r_ab derived."""
+    n = a.shape[0]
+    a64 = np.ascontiguousarray(a, dtype=np.float64)
+    b64 = a64 if b is None else np.ascontiguousarray(b, dtype=np.float64)
+    kb = kind_a if kind_b is None else kind_b
+    out = {name: np.zeros(n_bins) for name in ("k", "modes", "p_aa", "p_bb", "p_ab")}
+    _check(lib().oracle_spectra(n, float(box_len), _ptr(a64), int(kind_a), _ptr(b64), int(kb), int(n_bins),
+                                *[_ptr(out[x]) for x in ("k", "modes", "p_aa", "p_bb", "p_ab")]), "spectra")
+    with np.errstate(divide="ignore", invalid="ignore"):
+        out["delta2_aa"] = out["k"] ** 3 / (2 * np.pi ** 2) * out["p_aa"]
+        out["bias"] = np.sqrt(out["p_aa"] / out["p_bb"])
+        out["r"] = out["p_ab"] / np.sqrt(out["p_aa"] * out["p_bb"])
+    return out
 
 
 # ---------------------------------------------------------- abundance match --

@@ -21,6 +21,8 @@
  *                                     closed-form transform atan(k l)/k
  *   - abundance matching            : Sec. 3.4.2, the cumulative-mass equation
  *                                     (unnumbered) with weights 1+delta
+ *   - two-point statistics          : Sec. 2.3, Eqs. (deltaz), (Pk), (Dk), (bias),
+ *                                     (rcc): shell-averaged auto and cross spectra
  *
  * Readings of points the paper leaves open (each is listed in the design notes):
  *   R1 the spectral kernel is atan(k l_mfp)/k sampled at the discrete
@@ -35,7 +37,13 @@
  *   Z4 the cumulative mass is the exact sum (fixed point), F_n = RN(C_n)/RN(C_N);
  *   Z5 F = 1 maps to z = a_w;
  *   Z6 contract inversion by monotone table interpolation (geometry below);
- *   Z7 weights are 1+delta at z_mid (growth factor ratio 1).
+ *   Z7 weights are 1+delta at z_mid (growth factor ratio 1);
+ *   D1 a field enters the spectra as given, as an overdensity f/mean - 1, or as
+ *      the normalised redshift (f - mean)/(1 + mean) of Eq. (deltaz), the mean
+ *      being the volume average;
+ *   D2 spectra are shell averages over the full N^3 DFT grid: bin i holds the
+ *      modes with i - 1/2 <= |m~| < i + 1/2, P = (L^3/N^6) <Re(A_m conj B_m)>,
+ *      and the bin's k is (2 pi / L) times the mean |m~| of its modes.
  *
  * Parity pins for each routine live in tests/test_oracle_*.py.
  */
@@ -286,6 +294,83 @@ int oracle_radiation(int n, double box_len, const double* src, double l_mfp,
     free(re);
     free(im);
     return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Two-point statistics: Sec. 2.3, Eqs. (deltaz), (Pk), (bias), (rcc)        */
+/* ------------------------------------------------------------------------ */
+
+/* The field as it enters the spectra (reading D1): kind 0 as given, kind 1
+ * the overdensity f/mean - 1, kind 2 the normalised redshift of Eq. (deltaz),
+ * (f - mean)/(1 + mean), with the volume-weighted mean. */
+static int spectra_field(int64_t n3, const double* f, int kind, double* out) {
+    double mean = 0.0;
+    for (int64_t i = 0; i < n3; ++i) mean += f[i];
+    mean /= (double)n3;
+    for (int64_t i = 0; i < n3; ++i) {
+        if (kind == 0) out[i] = f[i];
+        else if (kind == 1) out[i] = f[i] / mean - 1.0;
+        else if (kind == 2) out[i] = (f[i] - mean) / (1.0 + mean);
+        else return OR_E_ARG;
+    }
+    return OR_OK;
+}
+
+/* Shell index of a mode with integer |m~|^2 = s2 (reading D2): the i with
+ * (2i - 1)^2 <= 4 s2 < (2i + 1)^2, decided in integers. */
+static int64_t shell_of(int64_t s2) {
+    int64_t i = (int64_t)floor(sqrt((double)s2));
+    while (i * i > s2) --i;
+    while ((i + 1) * (i + 1) <= s2) ++i;
+    if (4 * s2 >= (2 * i + 1) * (2 * i + 1)) ++i;
+    return i;
+}
+
+/* Auto and cross power spectra of fields a and b (Eq. Pk) in n_bins shells:
+ * k[i], modes[i] (number of DFT modes), p_aa, p_bb, p_ab (reading D2).
+ * Modes beyond the last shell are left out.  Naive DFTs, O(n^4). */
+int oracle_spectra(int n, double box_len, const double* a, int kind_a, const double* b, int kind_b, int n_bins,
+                   double* k, double* modes, double* p_aa, double* p_bb, double* p_ab) {
+    if (n < 1 || !(box_len > 0.0) || n_bins < 1 || !a || !b) return OR_E_ARG;
+    const int64_t n3 = (int64_t)n * n * n;
+    double* ar = (double*)malloc(sizeof(double) * (size_t)n3);
+    double* ai = (double*)calloc((size_t)n3, sizeof(double));
+    double* br = (double*)malloc(sizeof(double) * (size_t)n3);
+    double* bi = (double*)calloc((size_t)n3, sizeof(double));
+    int rc = OR_E_ARG;
+    if (ar && ai && br && bi && spectra_field(n3, a, kind_a, ar) == OR_OK &&
+        spectra_field(n3, b, kind_b, br) == OR_OK) {
+        oracle_dft3(n, ar, ai, -1);
+        oracle_dft3(n, br, bi, -1);
+        for (int i = 0; i < n_bins; ++i) k[i] = modes[i] = p_aa[i] = p_bb[i] = p_ab[i] = 0.0;
+        for (int mx = 0; mx < n; ++mx)
+            for (int my = 0; my < n; ++my)
+                for (int mz = 0; mz < n; ++mz) {
+                    const int64_t sx = signed_freq(mx, n), sy = signed_freq(my, n), sz = signed_freq(mz, n);
+                    const int64_t s2 = sx * sx + sy * sy + sz * sz;
+                    const int64_t sh = shell_of(s2);
+                    if (sh >= n_bins) continue;
+                    const int64_t i = ((int64_t)mx * n + my) * n + mz;
+                    modes[sh] += 1.0;
+                    k[sh] += sqrt((double)s2);
+                    p_aa[sh] += ar[i] * ar[i] + ai[i] * ai[i];
+                    p_bb[sh] += br[i] * br[i] + bi[i] * bi[i];
+                    p_ab[sh] += ar[i] * br[i] + ai[i] * bi[i];
+                }
+        const double vol = box_len * box_len * box_len / ((double)n3 * (double)n3);
+        const double k0 = 2.0 * M_PI / box_len;
+        for (int i = 0; i < n_bins; ++i) {
+            if (modes[i] > 0.0) {
+                k[i] = k0 * k[i] / modes[i];
+                p_aa[i] = vol * p_aa[i] / modes[i];
+                p_bb[i] = vol * p_bb[i] / modes[i];
+                p_ab[i] = vol * p_ab[i] / modes[i];
+            }
+        }
+        rc = OR_OK;
+    }
+    free(ar); free(ai); free(br); free(bi);
+    return rc;
 }
 
 /* Real-space periodic kernel g(n) = (1/n^3) sum_m Khat(k_m) e^{+2 pi i m.n/n},
