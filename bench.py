@@ -35,6 +35,8 @@ WORKLOADS = {
                              "(1 forward FFT, 8 inverse, 8 rankings, 32 inversions)"),
     "c4": dict(cfg=None, desc="64 boxes, N uniform in {64,96,128,192,256}, L=1.953125 N, random l_mfp and history, "
                              "one batch call replayed as a HIP graph"),
+    "spectra": dict(cfg="H", desc="cross power spectrum of z_re (normalised redshift) and density (overdensity) "
+                                  "of the 1024^3 box, 513 shells: two forward FFTs and the shell reduction"),
     "c5": dict(cfg=None, desc="Poisson requests at 20/s for 60 s, N in {128,256,512,1024} w.p. 0.4/0.3/0.2/0.1, "
                              "l_mfp and history from the 512^3 sweep sets; resident boxes, HBM-budget admission, "
                              "same-N batching"),
@@ -301,6 +303,37 @@ def bench_mixed(args) -> dict:
                                             "ms_per_step": 1e3 * el_s / args.steps}})
 
 
+def bench_spectra(args) -> dict:
+    """Two-point statistics of the 1024^3 box: P_zz, P_dd, P_zd, bias, r."""
+    import torch
+
+    import inputs
+    import paper_2109_10375_amd as amber
+
+    cfg = inputs.CONFIGS["H"]
+    dev = torch.device("cuda", 0)
+    w, S = inputs.make_box(cfg, device=dev, dtype=torch.float32)
+    plan = amber.Plan(cfg.n, cfg.box_len)
+    hist = amber.History.from_params(*cfg.histories[0])
+    (J,) = plan.radiation(S, [cfg.l_mfp[0]])
+    (z,) = plan.zre(J, w, [hist])
+    del J, S
+    torch.cuda.synchronize()
+    st = {}
+
+    def step():
+        st["r"] = plan.spectra(z, w, kind_a=amber._lib.FIELD_REDSHIFT, kind_b=amber._lib.FIELD_OVERDENSITY,
+                               n_bins=cfg.n // 2 + 1)
+
+    el, ms = _time_steps(step, args.steps, args.warmup)
+    r = st["r"]
+    return _common(args, "grid cells/s of the z_re x density cross spectrum at 1024^3", args.steps * cfg.n ** 3 / el,
+                   1e3 * el / args.steps, WORKLOADS["spectra"]["desc"],
+                   {"p50_ms": round(_pct(ms, 50), 3), "p99_ms": round(_pct(ms, 99), 3),
+                    "r_zd_at_k": {f"{float(r['k'][i]):.4f}": round(float(r["r"][i]), 4) for i in (1, 4, 16, 64, 256)},
+                    "b_zd_at_k": {f"{float(r['k'][i]):.4f}": round(float(r["bias"][i]), 4) for i in (1, 4, 16, 64, 256)}})
+
+
 def bench_serving(args) -> dict:
     """Poisson request stream served from resident boxes."""
     import torch
@@ -359,9 +392,10 @@ def main() -> int:
     import paper_2109_10375_amd as amber
 
     amber.lib()  # raises when the HIP library is missing: there is no fallback
-    if args.workload in ("c3", "c4", "c5"):
+    if args.workload in ("c3", "c4", "c5", "spectra"):
         torch.cuda.set_device(0)
-        out = {"c3": bench_sweep, "c4": bench_mixed, "c5": bench_serving}[args.workload](args)
+        out = {"c3": bench_sweep, "c4": bench_mixed, "c5": bench_serving,
+               "spectra": bench_spectra}[args.workload](args)
         print(json.dumps(out), flush=True)
         return 0
     wl = WORKLOADS[args.workload]

@@ -153,6 +153,33 @@ int amber_zre(amber_plan plan, const float* d_J, const float* d_w,
  * last calls that used this workspace in *status. */
 int amber_status(amber_plan plan, void* d_ws, void* stream, unsigned* status);
 
+/* ---- two-point statistics (Sec. 2.3) ------------------------------------- */
+
+/* How a field enters the spectra: as given, as the overdensity f/mean - 1
+ * (mean != 0), or as the normalised redshift (f - mean)/(1 + mean) of
+ * Eq. (deltaz); the mean is the volume average. */
+#define AMBER_FIELD_RAW 0
+#define AMBER_FIELD_OVERDENSITY 1
+#define AMBER_FIELD_REDSHIFT 2
+
+/* Workspace needed by amber_spectra on this plan. */
+size_t amber_spectra_workspace_bytes(amber_plan plan);
+
+/* Shell-averaged auto and cross power spectra of two N^3 FP32 fields
+ * (Eq. Pk; Dk, bias and rcc follow from them):
+ *   shell i (0 <= i < n_bins <= 1024) holds the modes of the full N^3 DFT grid
+ *   with i - 1/2 <= |m~| < i + 1/2 (m~ the signed integer frequency);
+ *   P_xy = (L^3/N^6) <Re(X_m conj Y_m)> over the shell, X the unnormalised DFT
+ *   of field x after its kind_x normalisation; k_i = (2 pi/L) <|m~|>.
+ * d_out: device, 8 * n_bins doubles, each row n_bins long: k | number of modes
+ * | P_aa | P_bb | P_ab | Delta^2_aa = k^3 P_aa/(2 pi^2) (Eq. Dk) | b_ab =
+ * sqrt(P_aa/P_bb) (Eq. bias) | r_ab = P_ab/sqrt(P_aa P_bb) (Eq. rcc); empty
+ * shells (and undefined ratios) are zero.  d_b may be NULL or equal to
+ * d_a (one transform).  Modes beyond the last shell are left out.  The sums
+ * are accumulated with FP64 atomics, so the last bits may differ between runs. */
+int amber_spectra(amber_plan plan, const float* d_a, int kind_a, const float* d_b, int kind_b, int n_bins,
+                  double* d_out, void* d_ws, size_t ws_bytes, void* stream);
+
 /* ---- batches (several boxes, mean free paths and histories) ------------- */
 
 /* One box of a batch: the radiation field for each of its n_lmfp mean free

@@ -23,8 +23,10 @@ SYMBOLS = [
     "amber_version", "amber_strerror", "amber_weibull_fit", "amber_weibull_from_coeffs",
     "amber_weibull_table", "amber_plan_create", "amber_plan_destroy", "amber_workspace_bytes",
     "amber_radiation", "amber_rank", "amber_zre", "amber_status", "amber_profile_begin",
-    "amber_profile_end", "amber_batch_workspace_bytes", "amber_batch_run",
+    "amber_profile_end", "amber_batch_workspace_bytes", "amber_batch_run", "amber_spectra_workspace_bytes",
+    "amber_spectra",
 ]
+FIELD_RAW, FIELD_OVERDENSITY, FIELD_REDSHIFT = 0, 1, 2
 
 
 class AmberWeibull(ctypes.Structure):
@@ -92,6 +94,9 @@ def lib() -> ctypes.CDLL:
         L.amber_batch_workspace_bytes.argtypes = [ctypes.POINTER(AmberBatchItem), i]
         L.amber_batch_workspace_bytes.restype = sz
         L.amber_batch_run.argtypes = [ctypes.POINTER(AmberBatchItem), i, vp, vp, sz, vp]
+        L.amber_spectra_workspace_bytes.argtypes = [vp]
+        L.amber_spectra_workspace_bytes.restype = sz
+        L.amber_spectra.argtypes = [vp, vp, i, vp, i, i, vp, vp, sz, vp]
         _lib = L
     return _lib
 
@@ -213,6 +218,25 @@ class Plan:
                                _dev_ptr(w, torch.float32, self.n3, "w"), harr, len(hists), ptrs,
                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "amber_zre")
         return list(out)
+
+    def spectra(self, a: torch.Tensor, b: torch.Tensor | None = None, kind_a: int = FIELD_RAW,
+                kind_b: int | None = None, n_bins: int | None = None) -> dict:
+        """amber_spectra: shell-averaged k, modes, P_aa, P_bb, P_ab, Delta^2_aa,
+        b_ab and r_ab (Sec. 2.3), as float64 tensors on the host."""
+        nb = self.n // 2 + 1 if n_bins is None else int(n_bins)
+        need = int(lib().amber_spectra_workspace_bytes(self._h))
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        out = torch.empty(8 * nb, dtype=torch.float64, device=self.device)
+        pa = _dev_ptr(a, torch.float32, self.n3, "a")
+        pb = _dev_ptr(b, torch.float32, self.n3, "b") if b is not None else None
+        _check(lib().amber_spectra(self._h, pa, int(kind_a), pb, int(kind_a if kind_b is None else kind_b), nb,
+                                   ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(self._ws.data_ptr()),
+                                   self._ws.numel(), _stream()), "amber_spectra")
+        rows = out.view(8, nb).cpu()
+        names = ("k", "modes", "p_aa", "p_bb", "p_ab", "delta2_aa", "bias", "r")
+        return {name: rows[i] for i, name in enumerate(names)}
 
     def profile_begin(self, capacity: int = 4096) -> None:
         """amber_profile_begin: time every kernel of the following calls."""

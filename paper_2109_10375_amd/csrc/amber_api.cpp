@@ -403,6 +403,35 @@ int amber_batch_run(const amber_batch_item* items, int n_items, unsigned* d_stat
     return AMBER_OK;
 }
 
+size_t amber_spectra_workspace_bytes(amber_plan plan) {
+    if (!plan) return 0;
+    return ws_layout(plan->n, 2).total;
+}
+
+int amber_spectra(amber_plan plan, const float* d_a, int kind_a, const float* d_b, int kind_b, int n_bins,
+                  double* d_out, void* d_ws, size_t ws_bytes, void* stream) {
+    if (!plan || !d_a || !d_out || !d_ws || n_bins < 1 || n_bins > 1024) return AMBER_E_ARG;
+    if (kind_a < 0 || kind_a > 2 || kind_b < 0 || kind_b > 2) return AMBER_E_ARG;
+    const WsLayout L = ws_layout(plan->n, 2);
+    if (ws_bytes < L.total) return AMBER_E_WORKSPACE;
+    unsigned char* ws = static_cast<unsigned char*>(d_ws);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    float2* sa = reinterpret_cast<float2*>(ws + L.spec_a);
+    float2* na = reinterpret_cast<float2*>(ws + L.nyq_a);
+    float2* sb = reinterpret_cast<float2*>(ws + L.spec_b);
+    float2* nb = reinterpret_cast<float2*>(ws + L.nyq_b);
+    int rc = fft_forward(plan, d_a, sa, na, s);
+    if (rc != AMBER_OK) return rc;
+    if (d_b && d_b != d_a) {
+        rc = fft_forward(plan, d_b, sb, nb, s);
+        if (rc != AMBER_OK) return rc;
+    } else {
+        sb = sa;
+        nb = na;
+    }
+    return spectra_bins(plan, sa, na, kind_a, sb, nb, kind_b, n_bins, d_out, s);
+}
+
 int amber_status(amber_plan plan, void* d_ws, void* stream, unsigned* status) {
     if (!plan || !d_ws || !status) return AMBER_E_ARG;
     const WsLayout L = ws_layout(plan->n, 1);

@@ -422,6 +422,45 @@ int run_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp
 
 }  // namespace
 
+// Forward real 3D FFT only (unnormalised): main[x][y][kz < N/2] and nyq[x][y].
+template <int N>
+int run_forward(const amber_plan_s* p, const float* d_src, float2* spec, float2* nyq, hipStream_t s) {
+    constexpr int H = N / 2, C = Shape<N>::C, N1 = Shape<N>::N1, ZL = Shape<N>::ZL, M1 = Shape<N>::M1;
+    const long long n_lines = (long long)N * N;
+    const float2* tw = p->d_tw;
+    const dim3 zblk(ZL * M1), cblk(C * N1);
+    const unsigned zgrid = (unsigned)((n_lines + ZL - 1) / ZL);
+    const ColGeom y_main{H, 1, (long long)N * H, C, H / C};
+    const ColGeom y_nyq{1, N, 0, (long long)C * N, N / C};
+    const ColGeom x_main{(long long)N * H, 1, H, C, H / C};
+    const ColGeom x_nyq{N, 1, 0, C, N / C};
+    const unsigned g_main = (unsigned)N * (H / C), g_nyq = (unsigned)(N / C);
+    const MulArgs none{0.f, 0.f, 0.f, 0};
+    AMBER_LAUNCH(p, "fft_z_r2c", (k_fft_z_r2c<N>), dim3(zgrid), zblk, s, d_src, spec, nyq, tw, n_lines);
+    AMBER_LAUNCH(p, "fft_y", (k_fft_cols<N, 0, false>), dim3(g_main), cblk, s, spec, spec, tw, y_main, none);
+    AMBER_LAUNCH(p, "fft_nyq_y", (k_fft_cols<N, 0, false>), dim3(g_nyq), cblk, s, nyq, nyq, tw, y_nyq, none);
+    AMBER_LAUNCH(p, "fft_x", (k_fft_cols<N, 0, false>), dim3(g_main), cblk, s, spec, spec, tw, x_main, none);
+    AMBER_LAUNCH(p, "fft_nyq_x", (k_fft_cols<N, 0, false>), dim3(g_nyq), cblk, s, nyq, nyq, tw, x_nyq, none);
+    AMBER_HIP_CHECK(hipGetLastError());
+    return AMBER_OK;
+}
+
+int fft_forward(const amber_plan_s* p, const float* d_src, float2* spec, float2* nyq, hipStream_t s) {
+    switch (p->n) {
+        case 8: return run_forward<8>(p, d_src, spec, nyq, s);
+        case 16: return run_forward<16>(p, d_src, spec, nyq, s);
+        case 32: return run_forward<32>(p, d_src, spec, nyq, s);
+        case 64: return run_forward<64>(p, d_src, spec, nyq, s);
+        case 96: return run_forward<96>(p, d_src, spec, nyq, s);
+        case 128: return run_forward<128>(p, d_src, spec, nyq, s);
+        case 192: return run_forward<192>(p, d_src, spec, nyq, s);
+        case 256: return run_forward<256>(p, d_src, spec, nyq, s);
+        case 512: return run_forward<512>(p, d_src, spec, nyq, s);
+        case 1024: return run_forward<1024>(p, d_src, spec, nyq, s);
+        default: return AMBER_E_SIZE;
+    }
+}
+
 int fft_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp, int n_lmfp,
                   float* const* d_J, unsigned char* ws, const WsLayout& L, hipStream_t s) {
     switch (p->n) {

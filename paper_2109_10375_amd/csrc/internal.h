@@ -129,6 +129,13 @@ __device__ __forceinline__ unsigned lb_walk(const unsigned* lb, long long tile, 
 int fft_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp, int n_lmfp,
                   float* const* d_J, unsigned char* ws, const WsLayout& L, hipStream_t s);
 
+// Forward transform only, into the given spectrum and Nyquist plane (fft.hip).
+int fft_forward(const amber_plan_s* p, const float* d_src, float2* spec, float2* nyq, hipStream_t s);
+
+// Shell-binned spectra of two forward transforms (spectra.hip).
+int spectra_bins(const amber_plan_s* p, const float2* spec_a, const float2* nyq_a, int kind_a,
+                 const float2* spec_b, const float2* nyq_b, int kind_b, int n_bins, double* d_out, hipStream_t s);
+
 // Ranking and matching launches (rank.hip, match.hip).
 int rank_sort(const amber_plan_s* p, const float* d_J, const float* d_w, unsigned char* ws,
               const WsLayout& L, hipStream_t s, int carry_weights, uint32_t* d_perm_out);
