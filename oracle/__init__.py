@@ -70,6 +70,10 @@ def lib():
         L.oracle_direct_convolution.argtypes = [i, d, p, d, p]
         L.oracle_dft_coeff_f32.argtypes = [i, p, i, i, i, pd, pd]
         L.oracle_spectra.argtypes = [i, d, p, i, p, i, i, p, p, p, p, p]
+        L.oracle_growth.argtypes = [d, d]
+        L.oracle_growth.restype = d
+        L.oracle_growth_table.argtypes = [d, d, i64, d, d, p]
+        L.oracle_zre_growth_f32.argtypes = [i64, p, p, d, d, i64, d, p, p, p, p]
         L.oracle_rank_f32.argtypes = [i64, p, p]
         L.oracle_rank_f64.argtypes = [i64, p, p]
         L.oracle_mass_fraction.argtypes = [i64, p, p, p]
@@ -215,6 +219,36 @@ def dft_coeff(field: np.ndarray, m: tuple[int, int, int]) -> complex:
     _check(lib().oracle_dft_coeff_f32(f.shape[0], _ptr(f), int(m[0]), int(m[1]), int(m[2]),
                                       ctypes.byref(re), ctypes.byref(im)), "dft_coeff")
     return complex(re.value, im.value)
+
+
+OMEGA_M = 0.3   # the paper's cosmology (Sec. 2)
+
+
+def growth(z: float, omega_m: float = OMEGA_M) -> float:
+    """Linear growth factor D(z) of flat Lambda-CDM, D -> a early (reading G1)."""
+    return float(lib().oracle_growth(float(z), float(omega_m)))
+
+
+def growth_table(H: "History", z_mid: float, omega_m: float = OMEGA_M) -> np.ndarray:
+    """G_j = D(z_j)/D(z_mid) at the inversion-table nodes of history H."""
+    G = np.empty(H.T + 1, dtype=np.float64)
+    _check(lib().oracle_growth_table(H.a, H.h, H.T, float(z_mid), float(omega_m), _ptr(G)), "growth_table")
+    return G
+
+
+def zre_growth(J: np.ndarray, w: np.ndarray, H: "History", G: np.ndarray):
+    """Growth-rescaled abundance matching (Sec. 3.4.2 with the growth factor,
+    readings G1, G2): returns (z_re FP32, z_re FP64)."""
+    j = np.ascontiguousarray(J, dtype=np.float32).reshape(-1)
+    ww = np.ascontiguousarray(w, dtype=np.float32).reshape(-1)
+    Gc = np.ascontiguousarray(G, dtype=np.float64)
+    if Gc.size != H.T + 1:
+        raise ValueError("growth table must have T + 1 entries")
+    z32 = np.empty(j.size, dtype=np.float32)
+    z64 = np.empty(j.size, dtype=np.float64)
+    _check(lib().oracle_zre_growth_f32(j.size, _ptr(j), _ptr(ww), H.a, H.h, H.T, H.z_top, _ptr(H.X), _ptr(Gc),
+                                       _ptr(z32), _ptr(z64)), "zre_growth")
+    return z32.reshape(J.shape), z64.reshape(J.shape)
 
 
 FIELD_RAW, FIELD_OVERDENSITY, FIELD_REDSHIFT = 0, 1, 2

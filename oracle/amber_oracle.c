@@ -23,6 +23,10 @@
  *                                     (unnumbered) with weights 1+delta
  *   - two-point statistics          : Sec. 2.3, Eqs. (deltaz), (Pk), (Dk), (bias),
  *                                     (rcc): shell-averaged auto and cross spectra
+ *   - growth-rescaled matching      : Sec. 3.4.2, the cumulative-mass equation
+ *                                     with delta_m(z_n) = D(z_n)/D(z_mid) delta_m,
+ *                                     D the linear growth factor of the paper's
+ *                                     flat cosmology (Sec. 2)
  *
  * Readings of points the paper leaves open (each is listed in the design notes):
  *   R1 the spectral kernel is atan(k l_mfp)/k sampled at the discrete
@@ -43,7 +47,14 @@
  *      being the volume average;
  *   D2 spectra are shell averages over the full N^3 DFT grid: bin i holds the
  *      modes with i - 1/2 <= |m~| < i + 1/2, P = (L^3/N^6) <Re(A_m conj B_m)>,
- *      and the bin's k is (2 pi / L) times the mean |m~| of its modes.
+ *      and the bin's k is (2 pi / L) times the mean |m~| of its modes;
+ *   G1 D(a) is the growing mode of a flat universe of matter and a
+ *      cosmological constant, normalised to a at early times; its ratio
+ *      G_j = D(z_j)/D(z_mid) is tabulated at the inversion-table nodes;
+ *   G2 with growth, rank n solves m_n(z)/M(z) = x_i(z) with the growth-weighted
+ *      masses m_n = n (1 - g) + g C_n (C_n the exact prefix of w = 1 + delta),
+ *      evaluated at the nodes with g = G_j, located by bisection over the node
+ *      index and interpolated linearly between the bracketing nodes.
  *
  * Parity pins for each routine live in tests/test_oracle_*.py.
  */
@@ -567,6 +578,98 @@ static double invert_table(double F, double a, double h, int64_t T, double z_top
     double dz = zj1 - zj;
     double z = zj + t * dz;
     return (z < z_top) ? z : z_top;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Growth-rescaled matching: Sec. 3.4.2 with delta_m(z) = D(z)/D(z_mid) delta_m */
+/* ------------------------------------------------------------------------ */
+
+/* Linear growth factor (reading G1): for a flat universe with matter density
+ * omega_m and a cosmological constant 1 - omega_m the growing mode is
+ *   D(a) = a 2F1(1/3, 1; 11/6; x),  x = -(1 - omega_m)/omega_m a^3,
+ * which equals a while matter dominates.  Pfaff's transformation
+ *   2F1(1/3, 1; 11/6; x) = (1 - x)^-1 2F1(3/2, 1; 11/6; x/(x - 1))
+ * turns x in (-inf, 0] into y = x/(x - 1) in [0, 1), where the power series
+ * sum_k (3/2)_k / (11/6)_k y^k converges; it is summed until a term no longer
+ * changes the sum. */
+double oracle_growth(double z, double omega_m) {
+    const double a = 1.0 / (1.0 + z);
+    const double x = -(1.0 - omega_m) / omega_m * (a * a * a);
+    const double y = x / (x - 1.0);
+    double term = 1.0, sum = 1.0;
+    for (int k = 0; k < 100000; ++k) {
+        term = term * ((1.5 + (double)k) / (11.0 / 6.0 + (double)k)) * y;
+        const double next = sum + term;
+        if (next == sum) break;
+        sum = next;
+    }
+    return a * (sum / (1.0 - x));
+}
+
+/* G_j = D(z_j)/D(z_mid) at the table nodes z_j = a + j h, j = 0..T. */
+int oracle_growth_table(double a, double h, int64_t T, double z_mid, double omega_m, double* G) {
+    if (!(h > 0.0) || T < 1 || !(omega_m > 0.0) || !(omega_m <= 1.0)) return OR_E_ARG;
+    const double dmid = oracle_growth(z_mid, omega_m);
+    for (int64_t j = 0; j <= T; ++j) G[j] = oracle_growth(a + (double)j * h, omega_m) / dmid;
+    return OR_OK;
+}
+
+/* h_j = m_j / M_j - X_j for the rank with k cells ionized (reading G2):
+ * m_j = (k s)(1 - G_j) + G_j cn, M_j = (N s)(1 - G_j) + G_j cN, where s = 2^-qmin
+ * puts the cell count in the units of the exact mass sums cn = RN(C_k) and
+ * cN = RN(C_N).  A fixed operation order, no fused multiply-add. */
+static double growth_gap(double ks, double ns, double cn, double cN, double G, double X) {
+    const double one_m = 1.0 - G;
+    const double m = ks * one_m + G * cn;
+    const double M = ns * one_m + G * cN;
+    return m / M - X;
+}
+
+/* z of one rank: z = a if h_0 > 0, z_top if h_T <= 0, else bisection on the
+ * node index keeping h_lo <= 0 < h_hi, then z = z_lo + t (z_hi - z_lo) with
+ * t = -h_lo / (h_hi - h_lo), clamped to z_top. */
+static double invert_growth(double ks, double ns, double cn, double cN, double a, double h, int64_t T,
+                            double z_top, const double* X, const double* G) {
+    const double h0 = growth_gap(ks, ns, cn, cN, G[0], X[0]);
+    if (h0 > 0.0) return a;
+    const double hT = growth_gap(ks, ns, cn, cN, G[T], X[T]);
+    if (!(hT > 0.0)) return z_top;
+    int64_t lo = 0, hi = T;
+    double hlo = h0, hhi = hT;
+    while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        const double hm = growth_gap(ks, ns, cn, cN, G[mid], X[mid]);
+        if (hm <= 0.0) { lo = mid; hlo = hm; } else { hi = mid; hhi = hm; }
+    }
+    const double zl = a + (double)lo * h;
+    const double zh = a + (double)hi * h;
+    const double t = -hlo / (hhi - hlo);
+    const double z = zl + t * (zh - zl);
+    return (z < z_top) ? z : z_top;
+}
+
+/* Full growth-rescaled match (readings G1, G2): ranking as in oracle_zre_*,
+ * exact prefix masses, per-rank bisection on the tables X and G. */
+int oracle_zre_growth_f32(int64_t n, const float* J, const float* w, double a, double h, int64_t T,
+                          double z_top, const double* X, const double* G, float* zre, double* zre64) {
+    uint32_t* perm = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    struct mass_scale ms;
+    int rc = rank_any(n, J, NULL, perm);
+    if (rc == OR_OK) rc = mass_scale_of(n, w, &ms);
+    if (rc == OR_OK) {
+        const double s = ldexp(1.0, -ms.qmin);
+        const double cN = (double)ms.total;
+        const double ns = (double)n * s;
+        u128 c = 0;
+        for (int64_t k = 0; k < n; ++k) {
+            c += scaled_weight(w[perm[k]], ms.qmin);
+            const double z = invert_growth((double)(k + 1) * s, ns, (double)c, cN, a, h, T, z_top, X, G);
+            if (zre) zre[perm[k]] = (float)z;
+            if (zre64) zre64[perm[k]] = z;
+        }
+    }
+    free(perm);
+    return rc;
 }
 
 /* Inversion of an array of mass fractions (used by the inversion pins). */
