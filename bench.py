@@ -29,6 +29,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 WORKLOADS = {
     "H": dict(cfg="H", desc="single box 1024^3, 2000 Mpc/h, 80M halos on [1e10,1e12] Msun/h, "
                             "l_mfp=3 Mpc/h, (z_mid, Delta_z, A_z)=(8, 4, 3)"),
+    "H_growth": dict(cfg="H", growth=True,
+                     desc="single box 1024^3 as the headline, matched with growth-rescaled overdensities "
+                          "delta(z) = D(z)/D(z_mid) delta (flat LCDM, Omega_m = 0.3)"),
     "c2": dict(cfg="c2", desc="single box 256^3, 500 Mpc/h, 1.3M halos on [1e10,1e12] Msun/h, "
                              "l_mfp=3 Mpc/h, (z_mid, Delta_z, A_z)=(8, 4, 3)"),
     "c3": dict(cfg="c3", desc="512^3 box, 1000 Mpc/h, 10M halos; 8 l_mfp x 4 histories in one batch call "
@@ -412,6 +415,8 @@ def main() -> int:
 
     plan = amber.Plan(n, cfg.box_len)
     hist = amber.History.from_params(*cfg.histories[0])
+    if wl.get("growth"):
+        hist = hist.with_growth(cfg.histories[0][0])
     J = torch.empty((n, n, n), dtype=torch.float32, device=dev)
     z = torch.empty((n, n, n), dtype=torch.float32, device=dev)
     plan.workspace(1)

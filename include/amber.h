@@ -74,12 +74,17 @@ typedef struct {
  *   table_n = T + 1 with T = ceil((z_top - a_w) / h); node j is z_j = a_w + j h
  *             and holds X_j = exp(-((z_j - a_w)/b_w)^c_w) (FP64)
  * d_table must point to T + 1 doubles on the device holding exactly the values
- * written by amber_weibull_table() for this struct. */
+ * written by amber_weibull_table() for this struct.
+ * d_growth selects the matching equation (Sec. 3.4.2): NULL weights every cell
+ * by its gas mass 1 + delta at z_mid; otherwise it points to T + 1 device
+ * doubles G_j = D(z_j)/D(z_mid) (amber_growth_table) and the overdensities are
+ * extrapolated linearly to each redshift, delta(z) = G delta. */
 typedef struct {
     double a_w, b_w, c_w;
     double h, z_top;
     int64_t table_n;
     const double* d_table;
+    const double* d_growth;
 } amber_weibull;
 
 /* ---- host-side helpers (no device work) -------------------------------- */
@@ -100,6 +105,14 @@ int amber_weibull_from_coeffs(double a_w, double b_w, double c_w, amber_weibull*
 /* Writes the T + 1 inversion-table values X_j into host_table (n_entries must
  * equal w->table_n).  The caller copies them to the device and sets d_table. */
 int amber_weibull_table(const amber_weibull* w, double* host_table, int64_t n_entries);
+
+/* Linear growth factor ratio at the table nodes, G_j = D(a_w + j h)/D(z_mid),
+ * j = 0..T, for a flat universe of matter density omega_m (0 < omega_m <= 1)
+ * and a cosmological constant; D is the growing mode, D = a while matter
+ * dominates: D(a) = a 2F1(1/3, 1; 11/6; -(1 - omega_m)/omega_m a^3) (the paper's
+ * cosmology, Sec. 2, has omega_m = 0.3).  n_entries must equal w->table_n. */
+int amber_growth_table(const amber_weibull* w, double z_mid, double omega_m, double* host_table,
+                       int64_t n_entries);
 
 /* ---- plans and workspace ------------------------------------------------ */
 
@@ -141,6 +154,14 @@ int amber_rank(amber_plan plan, const float* d_J, uint32_t* d_perm,
  *         z = z_j + t (z_{j+1} - z_j),  z = min(z, z_top),
  *         all in FP64 without fused multiply-add,
  *   d_zre[h][perm[n]] = (float) z_n for each history h.
+ * With a growth table (d_growth), rank n (k = n + 1 cells ionized) instead
+ * solves m_j / M_j = X_j with the growth-weighted masses
+ *   m_j = (k s)(1 - G_j) + G_j RN(C_n),  M_j = (N s)(1 - G_j) + G_j RN(C_N),
+ *   s = the unit of the exact sums (the cell count in the same units),
+ * h_j = m_j / M_j - X_j: z = a_w if h_0 > 0, z_top if h_T <= 0, otherwise
+ * bisection on the node index keeps h_lo <= 0 < h_hi down to adjacent nodes and
+ * z = z_lo + t (z_hi - z_lo), t = -h_lo / (h_hi - h_lo), min z_top (FP64,
+ * this operation order, no fused multiply-add).
  * d_J: N^3 FP32 intensities; d_w: N^3 FP32 gas-mass weights (1 + delta, > 0);
  * hist: host array of n_hist fitted histories with device tables; d_zre: host
  * array of n_hist device pointers to N^3 FP32 outputs.  The rank order and the

@@ -24,7 +24,7 @@ SYMBOLS = [
     "amber_weibull_table", "amber_plan_create", "amber_plan_destroy", "amber_workspace_bytes",
     "amber_radiation", "amber_rank", "amber_zre", "amber_status", "amber_profile_begin",
     "amber_profile_end", "amber_batch_workspace_bytes", "amber_batch_run", "amber_spectra_workspace_bytes",
-    "amber_spectra",
+    "amber_spectra", "amber_growth_table",
 ]
 FIELD_RAW, FIELD_OVERDENSITY, FIELD_REDSHIFT = 0, 1, 2
 
@@ -32,7 +32,7 @@ FIELD_RAW, FIELD_OVERDENSITY, FIELD_REDSHIFT = 0, 1, 2
 class AmberWeibull(ctypes.Structure):
     _fields_ = [("a_w", ctypes.c_double), ("b_w", ctypes.c_double), ("c_w", ctypes.c_double),
                 ("h", ctypes.c_double), ("z_top", ctypes.c_double), ("table_n", ctypes.c_int64),
-                ("d_table", ctypes.c_void_p)]
+                ("d_table", ctypes.c_void_p), ("d_growth", ctypes.c_void_p)]
 
 
 class AmberKernelTime(ctypes.Structure):
@@ -80,6 +80,7 @@ def lib() -> ctypes.CDLL:
         L.amber_weibull_fit.argtypes = [ctypes.POINTER(AmberHistory), ctypes.POINTER(AmberWeibull)]
         L.amber_weibull_from_coeffs.argtypes = [d, d, d, ctypes.POINTER(AmberWeibull)]
         L.amber_weibull_table.argtypes = [ctypes.POINTER(AmberWeibull), vp, i64]
+        L.amber_growth_table.argtypes = [ctypes.POINTER(AmberWeibull), d, d, vp, i64]
         L.amber_plan_create.argtypes = [ctypes.POINTER(vp), i, d]
         L.amber_plan_destroy.argtypes = [vp]
         L.amber_plan_destroy.restype = None
@@ -151,6 +152,29 @@ class History:
     @property
     def coeffs(self):
         return self.w.a_w, self.w.b_w, self.w.c_w
+
+    def with_growth(self, z_mid: float, omega_m: float = 0.3) -> "History":
+        """The same history matched with growth-rescaled overdensities
+        (amber_growth_table: G_j = D(z_j)/D(z_mid) on the device)."""
+        w = AmberWeibull.from_buffer_copy(self.w)
+        h = History.__new__(History)
+        h.w = w
+        h.table = self.table
+        host = torch.empty(w.table_n, dtype=torch.float64)
+        _check(lib().amber_growth_table(ctypes.byref(w), float(z_mid), float(omega_m),
+                                        ctypes.c_void_p(host.data_ptr()), w.table_n), "amber_growth_table")
+        h.growth = host.to(self.table.device)
+        h.w.d_table = self.table.data_ptr()
+        h.w.d_growth = h.growth.data_ptr()
+        return h
+
+    @staticmethod
+    def growth_table_host(w: AmberWeibull, z_mid: float, omega_m: float = 0.3) -> torch.Tensor:
+        """The library's host growth table for a fitted history (no GPU work)."""
+        host = torch.empty(w.table_n, dtype=torch.float64)
+        _check(lib().amber_growth_table(ctypes.byref(w), float(z_mid), float(omega_m),
+                                        ctypes.c_void_p(host.data_ptr()), w.table_n), "amber_growth_table")
+        return host
 
 
 class Plan:

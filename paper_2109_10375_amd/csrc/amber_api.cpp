@@ -149,6 +149,7 @@ int amber_weibull_from_coeffs(double a_w, double b_w, double c_w, amber_weibull*
     out->z_top = top;
     out->table_n = (int64_t)std::ceil(span / h) + 1;
     out->d_table = nullptr;
+    out->d_growth = nullptr;
     return AMBER_OK;
 }
 
@@ -182,6 +183,34 @@ int amber_weibull_table(const amber_weibull* w, double* host_table, int64_t n_en
         const double z = a + (double)j * h;
         host_table[j] = std::exp(-std::pow((z - a) / b, c));
     }
+    return AMBER_OK;
+}
+
+// Growing mode of flat Lambda-CDM, normalised to a early: a 2F1(1/3, 1; 11/6; x),
+// x = -(1 - om)/om a^3, summed after Pfaff's transformation as
+// a / (1 - x) * sum_k (3/2)_k / (11/6)_k y^k, y = x / (x - 1), until a term no
+// longer changes the sum.
+static double growth_factor(double z, double om) {
+#pragma clang fp contract(off)
+    const double a = 1.0 / (1.0 + z);
+    const double x = -(1.0 - om) / om * (a * a * a);
+    const double y = x / (x - 1.0);
+    double term = 1.0, sum = 1.0;
+    for (int k = 0; k < 100000; ++k) {
+        term = term * ((1.5 + (double)k) / (11.0 / 6.0 + (double)k)) * y;
+        const double next = sum + term;
+        if (next == sum) break;
+        sum = next;
+    }
+    return a * (sum / (1.0 - x));
+}
+
+int amber_growth_table(const amber_weibull* w, double z_mid, double omega_m, double* host_table,
+                       int64_t n_entries) {
+    if (!w || !host_table || n_entries != w->table_n || n_entries < 2) return AMBER_E_ARG;
+    if (!(omega_m > 0.0) || !(omega_m <= 1.0) || !std::isfinite(z_mid) || !(z_mid > -1.0)) return AMBER_E_ARG;
+    const double dmid = growth_factor(z_mid, omega_m);
+    for (int64_t j = 0; j < n_entries; ++j) host_table[j] = growth_factor(w->a_w + (double)j * w->h, omega_m) / dmid;
     return AMBER_OK;
 }
 

@@ -96,6 +96,7 @@ struct HistArg {
     double a, b, inv_c, h, z_top;
     long long T;
     const double* X;
+    const double* G;  // growth ratios D(z_j)/D(z_mid) at the nodes, or null
     float* out;
 };
 
@@ -150,6 +151,47 @@ __device__ __forceinline__ double interpolate_xy(double F, long long j, double x
     const double t = (den != 0.0) ? (xj - F) / den : 0.0;
     const double dz = zj1 - zj;
     const double z = zj + t * dz;
+    return (z < z_top) ? z : z_top;
+}
+
+// Growth-rescaled matching (Sec. 3.4.2 with delta(z) = D(z)/D(z_mid) delta):
+// rank with k cells ionized, ks = k s and ns = N s its count and the total in
+// the units s of the exact sums, cn = RN(C_k), cN = RN(C_N):
+//   h_j = (ks (1 - G_j) + G_j cn) / (ns (1 - G_j) + G_j cN) - X_j,
+// z = a if h_0 > 0, z_top if h_T <= 0, else bisection on the node index keeping
+// h_lo <= 0 < h_hi, then linear interpolation of h between the two nodes.
+__device__ __forceinline__ double growth_gap(double ks, double ns, double cn, double cN, double G, double X) {
+#pragma clang fp contract(off)
+    const double one_m = 1.0 - G;
+    const double m = ks * one_m + G * cn;
+    const double M = ns * one_m + G * cN;
+    return m / M - X;
+}
+
+__device__ double invert_growth(double ks, double ns, double cn, double cN, double a, double h, long long T,
+                                double z_top, const double* __restrict__ X, const double* __restrict__ G) {
+#pragma clang fp contract(off)
+    const double h0 = growth_gap(ks, ns, cn, cN, G[0], X[0]);
+    if (h0 > 0.0) return a;
+    const double hT = growth_gap(ks, ns, cn, cN, G[T], X[T]);
+    if (!(hT > 0.0)) return z_top;
+    long long lo = 0, hi = T;
+    double hlo = h0, hhi = hT;
+    while (hi - lo > 1) {
+        const long long mid = lo + (hi - lo) / 2;
+        const double hm = growth_gap(ks, ns, cn, cN, G[mid], X[mid]);
+        if (hm <= 0.0) {
+            lo = mid;
+            hlo = hm;
+        } else {
+            hi = mid;
+            hhi = hm;
+        }
+    }
+    const double zl = a + (double)lo * h;
+    const double zh = a + (double)hi * h;
+    const double t = -hlo / (hhi - hlo);
+    const double z = zl + t * (zh - zl);
     return (z < z_top) ? z : z_top;
 }
 
@@ -451,13 +493,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
     A run = A::of128(tile_excl) + wave_excl + thread_excl;
     const u128 total = {ctrl->total_lo, ctrl->total_hi};
     const double tot = u128_to_f64(total);
-    double F[kPer];
+    double cn[kPer];  // RN of the exact inclusive prefix of each rank
     unsigned pos[kPer];
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const bool live = rb[j] != 0xffffffffu;
         if (live) run = run + A::of(wf[j], qmin);
-        F[j] = __ddiv_rn(run.to_f64(), tot);
+        cn[j] = run.to_f64();
         pos[j] = live ? loff[rb[j] >> 16] + (rb[j] & 0xffffu) : 0xffffffffu;
         if (pos[j] >= (unsigned)kScanTile) pos[j] = 0xffffffffu;  // unreachable for consistent counts
         if (pos[j] != 0xffffffffu) stage[pos[j]] = idx[j];
@@ -472,19 +514,24 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
     // (the first ranks, where F grows fast relative to itself) walk exactly
     // from their own guess.  T >= 2^21.
     auto window = [&](const HistArg& H, long long& gl, double* x) {
-        gl = guess_node(F[kPer / 2], H) - 3;
+        gl = guess_node(__ddiv_rn(cn[kPer / 2], tot), H) - 3;
         gl = gl < 0 ? 0 : (gl > H.T - 7 ? H.T - 7 : gl);
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = H.X[gl + e];
     };
     // z of the thread's ranks for one history
+    const double unit = ldexp(1.0, -qmin);  // one cell in the units of the exact sums
+    const double ns = (double)n * unit;
     auto z_of = [&](const HistArg& H, long long gl, const double* x, float* zf) {
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            const double f = F[j];
+            const double f = __ddiv_rn(cn[j], tot);  // F_n = RN(C_n) / RN(C_N)
             double z = 0.0;
             if (pos[j] != 0xffffffffu) {
-                if (x[0] >= f && x[7] < f) {
+                if (H.G) {
+                    const double ks = (double)(p0 + j + 1) * unit;
+                    z = invert_growth(ks, ns, cn[j], tot, H.a, H.h, H.T, H.z_top, H.X, H.G);
+                } else if (x[0] >= f && x[7] < f) {
                     int kk = 0;
 #pragma unroll
                     for (int e = 1; e < 7; ++e) kk += (x[e] >= f) ? 1 : 0;  // X non-increasing
@@ -504,14 +551,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
             zf[j] = (float)z;
         }
     };
-    // The first history's z is computed before any store is issued: a wait
+    // With one history its z is computed before any store is issued: a wait
     // for a load issued before stores that may or may not execute would also
-    // wait for those stores.
+    // wait for those stores.  (Several histories share one code path below,
+    // which keeps the kernel's registers in check.)
     float zf0[kPer];
-    {
-        long long gl0;
-        double x0[8];
-        window(hs.h[0], gl0, x0);
+    if constexpr (NH == 1) {
+        long long gl0 = 0;
+        double x0[8] = {};
+        if (!hs.h[0].G) window(hs.h[0], gl0, x0);
         z_of(hs.h[0], gl0, x0, zf0);
     }
 
@@ -537,15 +585,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
         const HistArg& H = hs.h[hh];
         float* __restrict__ out = hh == 0 ? part_z0 : (hh == 1 ? part_z1 : part_z2);
         __syncthreads();  // the previous contents of the staging buffer are consumed
-        if (hh == 0) {
+        if (NH == 1) {
 #pragma unroll
             for (int j = 0; j < kPer; ++j)
                 if (pos[j] != 0xffffffffu) stage[pos[j]] = __float_as_uint(zf0[j]);
         } else {
-            long long gl;
-            double x[8];
+            long long gl = 0;
+            double x[8] = {};
             float zf[kPer];
-            window(H, gl, x);
+            if (!H.G) window(H, gl, x);
             z_of(H, gl, x, zf);
 #pragma unroll
             for (int j = 0; j < kPer; ++j)
@@ -740,7 +788,7 @@ int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, flo
         for (int i = 0; i < hs.n; ++i) {
             const amber_weibull& w = hist[h0 + i];
             hs.h[i] = HistArg{w.a_w, w.b_w, 1.0 / w.c_w, w.h, w.z_top, (long long)(w.table_n - 1), w.d_table,
-                              d_zre[h0 + i]};
+                              w.d_growth, d_zre[h0 + i]};
         }
         if (g > 0) AMBER_LAUNCH(p, "match_clear", k_clear, dim3(1), dim3(256), s, fill1, kL1);
 #define AMBER_SCAN(NHV)                                                                                      \

@@ -113,3 +113,18 @@ def test_batch_entry_points_check_their_arguments_on_the_host():
     assert L.amber_batch_run(items, 0, None, ctypes.c_void_p(1), 1, None) == amber._lib.E_ARG
     # an item with no plan is rejected before anything is enqueued
     assert L.amber_batch_run(items, 1, None, ctypes.c_void_p(1), 1, None) == amber._lib.E_ARG
+
+
+@pytest.mark.parametrize("hist,z_mid", [((8.0, 4.0, 3.0), 8.0), ((7.83, 6.54, 2.33), 7.83), ((9.0, 2.0, 1.5), 9.0)])
+def test_growth_table_identical_to_oracle(hist, z_mid):
+    """The library's growth ratios at the table nodes equal the oracle's byte
+    for byte (the same series, written separately on each side), so growth
+    matching can be compared bit for bit."""
+    amber = _amber()
+    H = oracle.History.from_params(*hist)
+    w = amber._lib.AmberWeibull()
+    assert amber.lib().amber_weibull_from_coeffs(H.a, H.b, H.c, ctypes.byref(w)) == 0
+    g_lib = amber.History.growth_table_host(w, z_mid).numpy()
+    g_or = oracle.growth_table(H, z_mid)
+    assert g_lib.shape == g_or.shape
+    assert np.array_equal(g_lib.view(np.uint64), g_or.view(np.uint64))
