@@ -70,6 +70,8 @@ def lib():
         L.oracle_direct_convolution.argtypes = [i, d, p, d, p]
         L.oracle_dft_coeff_f32.argtypes = [i, p, i, i, i, pd, pd]
         L.oracle_spectra.argtypes = [i, d, p, i, p, i, i, p, p, p, p, p]
+        L.oracle_radiation_from_halos.argtypes = [i, d, i64, p, p, i, i, d, p]
+        L.oracle_deposit.argtypes = [i, d, i64, p, p, i, d, p]
         L.oracle_growth.argtypes = [d, d]
         L.oracle_growth.restype = d
         L.oracle_growth_table.argtypes = [d, d, i64, d, d, p]
@@ -219,6 +221,34 @@ def dft_coeff(field: np.ndarray, m: tuple[int, int, int]) -> complex:
     _check(lib().oracle_dft_coeff_f32(f.shape[0], _ptr(f), int(m[0]), int(m[1]), int(m[2]),
                                       ctypes.byref(re), ctypes.byref(im)), "dft_coeff")
     return complex(re.value, im.value)
+
+
+NGP, CIC, TSC = 1, 2, 3
+
+
+def deposit(n: int, box_len: float, pos: np.ndarray, mass: np.ndarray, p: int, shift: float = 0.0) -> np.ndarray:
+    """Mass assignment of a halo catalogue (positions (n_halo, 3) in [0, L))
+    to an n^3 mesh with window order p (reading A1), positions shifted by
+    ``shift`` cells."""
+    ps = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1)
+    ms = np.ascontiguousarray(mass, dtype=np.float32)
+    mesh = np.empty((n, n, n), dtype=np.float64)
+    _check(lib().oracle_deposit(n, float(box_len), ms.size, _ptr(ps), _ptr(ms), int(p), float(shift), _ptr(mesh)),
+           "deposit")
+    return mesh
+
+
+def radiation_from_halos(n: int, box_len: float, pos: np.ndarray, mass: np.ndarray, p: int, interlace: bool,
+                         l_mfp: float) -> np.ndarray:
+    """J of a halo catalogue: interlaced, deconvolved mass assignment (Sec.
+    3.2.1, Eqs. interlace, Wofk; readings A1, A2) convolved with the radiation
+    kernel (Sec. 3.4.1)."""
+    ps = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1)
+    ms = np.ascontiguousarray(mass, dtype=np.float32)
+    J = np.empty((n, n, n), dtype=np.float64)
+    _check(lib().oracle_radiation_from_halos(n, float(box_len), ms.size, _ptr(ps), _ptr(ms), int(p),
+                                             1 if interlace else 0, float(l_mfp), _ptr(J)), "radiation_from_halos")
+    return J
 
 
 OMEGA_M = 0.3   # the paper's cosmology (Sec. 2)

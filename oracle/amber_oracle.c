@@ -23,6 +23,10 @@
  *                                     (unnumbered) with weights 1+delta
  *   - two-point statistics          : Sec. 2.3, Eqs. (deltaz), (Pk), (Dk), (bias),
  *                                     (rcc): shell-averaged auto and cross spectra
+ *   - halo source construction      : Sec. 3.2.1, Eqs. (interlace), (Wofk): mass
+ *                                     assignment (NGP, CIC, TSC) to two meshes
+ *                                     staggered by half a cell, combined and
+ *                                     deconvolved in Fourier space
  *   - growth-rescaled matching      : Sec. 3.4.2, the cumulative-mass equation
  *                                     with delta_m(z_n) = D(z_n)/D(z_mid) delta_m,
  *                                     D the linear growth factor of the paper's
@@ -48,6 +52,16 @@
  *   D2 spectra are shell averages over the full N^3 DFT grid: bin i holds the
  *      modes with i - 1/2 <= |m~| < i + 1/2, P = (L^3/N^6) <Re(A_m conj B_m)>,
  *      and the bin's k is (2 pi / L) times the mean |m~| of its modes;
+ *   A1 halo positions are in length units in [0, L), periodic; mesh cell i
+ *      spans [i, i+1) l_c with its node at the centre; NGP takes the cell
+ *      holding the halo, CIC and TSC the 2 and 3 nearest nodes per axis with
+ *      the linear and quadratic weights; the second mesh gets the positions
+ *      shifted by +l_c/2 on every axis;
+ *   A2 the combined spectrum of Eq. (interlace) is formed on the full DFT grid
+ *      with k_d = (2 pi / L) m~_d (m~ the signed frequency, +N/2 at the
+ *      Nyquist index) and the field is the real part of its inverse transform
+ *      (the Hermitian part of the spectrum); without interlacing it is the
+ *      first mesh's spectrum over W_pm;
  *   G1 D(a) is the growing mode of a flat universe of matter and a
  *      cosmological constant, normalised to a at early times; its ratio
  *      G_j = D(z_j)/D(z_mid) is tabulated at the inversion-table nodes;
@@ -382,6 +396,119 @@ int oracle_spectra(int n, double box_len, const double* a, int kind_a, const dou
     }
     free(ar); free(ai); free(br); free(bi);
     return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Halo source fields: Sec. 3.2.1, Eqs. (interlace), (Wofk)                  */
+/* ------------------------------------------------------------------------ */
+
+/* Mass assignment of one coordinate (in cell units, nodes at i + 1/2) with a
+ * window of order p (reading A1): the first node index and up to 3 weights. */
+static int assign_1d(double x, int p, int64_t* i0, double* wgt) {
+    if (p == 1) {
+        *i0 = (int64_t)floor(x);
+        wgt[0] = 1.0;
+        return 1;
+    }
+    if (p == 2) {
+        const double d = x - 0.5;
+        const double f = floor(d);
+        *i0 = (int64_t)f;
+        wgt[1] = d - f;
+        wgt[0] = 1.0 - wgt[1];
+        return 2;
+    }
+    /* TSC: nearest node c = floor(x), offset u = x - (c + 1/2) in [-1/2, 1/2) */
+    const double c = floor(x);
+    const double u = x - (c + 0.5);
+    *i0 = (int64_t)c - 1;
+    wgt[0] = 0.5 * (0.5 - u) * (0.5 - u);
+    wgt[1] = 0.75 - u * u;
+    wgt[2] = 0.5 * (0.5 + u) * (0.5 + u);
+    return 3;
+}
+
+static int64_t wrap(int64_t i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+/* Deposit halos (positions pos[3h..3h+2] in [0, L), masses) onto an n^3 mesh
+ * with window order p, positions shifted by `shift` cells on every axis. */
+static void deposit(int n, double box_len, int64_t n_halo, const float* pos, const float* mass, int p,
+                    double shift, double* mesh) {
+    const int64_t n3 = (int64_t)n * n * n;
+    for (int64_t i = 0; i < n3; ++i) mesh[i] = 0.0;
+    const double to_cell = (double)n / box_len;
+    for (int64_t h = 0; h < n_halo; ++h) {
+        int64_t i0[3];
+        double w[3][3];
+        int cnt = 0;
+        for (int d = 0; d < 3; ++d) cnt = assign_1d((double)pos[3 * h + d] * to_cell + shift, p, &i0[d], w[d]);
+        for (int a = 0; a < cnt; ++a)
+            for (int b = 0; b < cnt; ++b)
+                for (int c = 0; c < cnt; ++c) {
+                    const int64_t ix = wrap(i0[0] + a, n), iy = wrap(i0[1] + b, n), iz = wrap(i0[2] + c, n);
+                    mesh[(ix * n + iy) * n + iz] += (double)mass[h] * w[0][a] * w[1][b] * w[2][c];
+                }
+    }
+}
+
+/* Radiation field of a halo catalogue (Sec. 3.2.1 and Sec. 3.4.1, readings A1,
+ * A2, R1, R2): meshes rho_1 (positions as given) and rho_2 (shifted by +l_c/2),
+ * rho(k) = [rho_1(k) + e^{i k.dx} rho_2(k)] / 2 / W_pm(k) (or rho_1(k)/W_pm(k)
+ * without interlacing), then J = Re IDFT[rho(k) Khat(|k|)] / n^3.  Naive DFTs. */
+int oracle_radiation_from_halos(int n, double box_len, int64_t n_halo, const float* pos, const float* mass, int p,
+                                int interlace, double l_mfp, double* J) {
+    if (n < 1 || !(box_len > 0.0) || !(l_mfp > 0.0) || p < 1 || p > 3 || n_halo < 0) return OR_E_ARG;
+    const int64_t n3 = (int64_t)n * n * n;
+    double* ar = (double*)malloc(sizeof(double) * (size_t)n3);
+    double* ai = (double*)calloc((size_t)n3, sizeof(double));
+    double* br = (double*)malloc(sizeof(double) * (size_t)n3);
+    double* bi = (double*)calloc((size_t)n3, sizeof(double));
+    if (!ar || !ai || !br || !bi) { free(ar); free(ai); free(br); free(bi); return OR_E_ARG; }
+    deposit(n, box_len, n_halo, pos, mass, p, 0.0, ar);
+    oracle_dft3(n, ar, ai, -1);
+    if (interlace) {
+        deposit(n, box_len, n_halo, pos, mass, p, 0.5, br);
+        oracle_dft3(n, br, bi, -1);
+    }
+    const double k0 = 2.0 * M_PI / box_len;
+    for (int mx = 0; mx < n; ++mx)
+        for (int my = 0; my < n; ++my)
+            for (int mz = 0; mz < n; ++mz) {
+                const int s[3] = {signed_freq(mx, n), signed_freq(my, n), signed_freq(mz, n)};
+                double W = 1.0, theta = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    const double arg = M_PI * (double)s[d] / (double)n;   /* k_d l_c / 2 */
+                    const double sinc = (s[d] == 0) ? 1.0 : sin(arg) / arg;
+                    W *= pow(sinc, (double)p);
+                    theta += arg;                                           /* k_d dx_d, dx_d = l_c/2 */
+                }
+                const int64_t i = ((int64_t)mx * n + my) * n + mz;
+                double xr = ar[i], xi = ai[i];
+                if (interlace) {
+                    const double c = cos(theta), sn = sin(theta);
+                    xr = 0.5 * (ar[i] + c * br[i] - sn * bi[i]);
+                    xi = 0.5 * (ai[i] + c * bi[i] + sn * br[i]);
+                }
+                const double k = k0 * sqrt((double)s[0] * s[0] + (double)s[1] * s[1] + (double)s[2] * s[2]);
+                const double g = oracle_kernel_hat(k, l_mfp) / W;
+                ar[i] = xr * g;
+                ai[i] = xi * g;
+            }
+    oracle_dft3(n, ar, ai, +1);
+    for (int64_t i = 0; i < n3; ++i) J[i] = ar[i] / (double)n3;
+    free(ar); free(ai); free(br); free(bi);
+    return OR_OK;
+}
+
+/* The mesh of one deposit (for the assignment pins). */
+int oracle_deposit(int n, double box_len, int64_t n_halo, const float* pos, const float* mass, int p,
+                   double shift, double* mesh) {
+    if (n < 1 || !(box_len > 0.0) || p < 1 || p > 3) return OR_E_ARG;
+    deposit(n, box_len, n_halo, pos, mass, p, shift, mesh);
+    return OR_OK;
 }
 
 /* Real-space periodic kernel g(n) = (1/n^3) sum_m Khat(k_m) e^{+2 pi i m.n/n},
