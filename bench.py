@@ -38,6 +38,8 @@ WORKLOADS = {
                              "(1 forward FFT, 8 inverse, 8 rankings, 32 inversions)"),
     "c4": dict(cfg=None, desc="64 boxes, N uniform in {64,96,128,192,256}, L=1.953125 N, random l_mfp and history, "
                              "one batch call replayed as a HIP graph"),
+    "H_halos": dict(cfg="H", desc="1024^3 box from its 80M-halo catalogue: CIC deposit on two interlaced meshes, "
+                                  "deconvolution, radiation and matching (l_mfp=3, (8, 4, 3))"),
     "spectra": dict(cfg="H", desc="cross power spectrum of z_re (normalised redshift) and density (overdensity) "
                                   "of the 1024^3 box, 513 shells: two forward FFTs and the shell reduction"),
     "c5": dict(cfg=None, desc="Poisson requests at 20/s for 60 s, N in {128,256,512,1024} w.p. 0.4/0.3/0.2/0.1, "
@@ -337,6 +339,40 @@ def bench_spectra(args) -> dict:
                     "b_zd_at_k": {f"{float(r['k'][i]):.4f}": round(float(r["bias"][i]), 4) for i in (1, 4, 16, 64, 256)}})
 
 
+def bench_halos(args) -> dict:
+    """The headline box built from its halo catalogue on the GPU each step."""
+    import torch
+
+    import inputs
+    import paper_2109_10375_amd as amber
+
+    cfg = inputs.CONFIGS["H"]
+    dev = torch.device("cuda", 0)
+    n = cfg.n
+    w = inputs.make_density(n, inputs.config_seed(cfg.index, 0), device=dev, dtype=torch.float32).to(torch.float32)
+    pos, mass = inputs.make_halos(cfg, device=dev, w=w)
+    plan = amber.Plan(n, cfg.box_len)
+    hist = amber.History.from_params(*cfg.histories[0])
+    J = torch.empty((n, n, n), dtype=torch.float32, device=dev)
+    z = torch.empty_like(J)
+
+    def step():
+        plan.radiation_from_halos(pos, mass, [cfg.l_mfp[0]], scheme=amber._lib.ASSIGN_CIC, interlace=True, out=[J])
+        plan.zre(J, w, [hist], out=[z])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile_begin(64 * args.steps)
+    el, ms = _time_steps(step, args.steps, 0)
+    prof = plan.profile_end()
+    return _common(args, "grid cells/s from a halo catalogue (deposit + radiation + zre match) at 1024^3",
+                   args.steps * n ** 3 / el, 1e3 * el / args.steps, WORKLOADS["H_halos"]["desc"],
+                   {"p50_ms": round(_pct(ms, 50), 3), "p99_ms": round(_pct(ms, 99), 3), "n_halo": cfg.n_halo,
+                    "kernels_ms_per_step": {k: round(t / args.steps, 4)
+                                            for k, (c, t) in sorted(prof.items(), key=lambda kv: -kv[1][1])}})
+
+
 def bench_serving(args) -> dict:
     """Poisson request stream served from resident boxes."""
     import torch
@@ -395,10 +431,10 @@ def main() -> int:
     import paper_2109_10375_amd as amber
 
     amber.lib()  # raises when the HIP library is missing: there is no fallback
-    if args.workload in ("c3", "c4", "c5", "spectra"):
+    if args.workload in ("c3", "c4", "c5", "spectra", "H_halos"):
         torch.cuda.set_device(0)
-        out = {"c3": bench_sweep, "c4": bench_mixed, "c5": bench_serving,
-               "spectra": bench_spectra}[args.workload](args)
+        out = {"c3": bench_sweep, "c4": bench_mixed, "c5": bench_serving, "spectra": bench_spectra,
+               "H_halos": bench_halos}[args.workload](args)
         print(json.dumps(out), flush=True)
         return 0
     wl = WORKLOADS[args.workload]

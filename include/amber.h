@@ -139,6 +139,29 @@ size_t amber_workspace_bytes(amber_plan plan, int n_lmfp);
 int amber_radiation(amber_plan plan, const float* d_src, const double* l_mfp, int n_lmfp,
                     float* const* d_J, void* d_ws, size_t ws_bytes, void* stream);
 
+/* Mass-assignment windows for halo sources (Sec. 3.2.1, Eq. Wofk: p = 1, 2, 3). */
+#define AMBER_ASSIGN_NGP 1
+#define AMBER_ASSIGN_CIC 2
+#define AMBER_ASSIGN_TSC 3
+
+/* Workspace needed by amber_radiation_from_halos on this plan. */
+size_t amber_halo_workspace_bytes(amber_plan plan);
+
+/* Radiation field of a halo catalogue (Sec. 3.2.1 and Sec. 3.4.1):
+ *   the halo masses are assigned with window p (scheme) to mesh 1 and, when
+ *   interlace is set, with the positions shifted by +l_c/2 on every axis to
+ *   mesh 2 (cell i spans [i, i+1) l_c, node at its centre, periodic);
+ *   S(k) = [A(k) + e^{i k.dx} B(k)] / 2 / W(k) (Eq. interlace), or A(k)/W(k)
+ *   without interlacing, W(k) = prod_d [sin(k_d l_c/2)/(k_d l_c/2)]^p (Eq. Wofk),
+ *   k_d = (2 pi/L) m~_d (m~ the signed frequency, +N/2 at the Nyquist index);
+ *   J_l = Re IDFT[S(k) Khat(|k|; l)] / N^3 for each l_mfp, as amber_radiation.
+ * d_pos: device, n_halo x 3 FP32 positions in [0, box_len) (others wrap);
+ * d_mass: device, n_halo FP32 masses.  The deposit uses FP32 atomics, so the
+ * last bits of J may differ between runs. */
+int amber_radiation_from_halos(amber_plan plan, const float* d_pos, const float* d_mass, int64_t n_halo,
+                               int scheme, int interlace, const double* l_mfp, int n_lmfp, float* const* d_J,
+                               void* d_ws, size_t ws_bytes, void* stream);
+
 /* Rank order of Sec. 3.4.2: d_perm[n] = index of the cell of rank n, ranking by
  * d_J descending, ties by ascending cell index, -0 equal to +0.  NaN sets
  * AMBER_STATUS_NAN_J.  d_perm: N^3 uint32 outputs. */

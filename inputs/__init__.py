@@ -14,6 +14,7 @@ from .synth import (  # noqa: F401
     config_seed,
     make_box,
     make_density,
+    make_halos,
     make_intensity,
     make_weights_edge,
 )

@@ -161,6 +161,30 @@ def make_box(cfg: BoxConfig, box: int = 0, device="cpu", dtype=None, chunk: int 
     return w.to(torch.float32).contiguous(), S.view(n, n, n).to(torch.float32).contiguous()
 
 
+def make_halos(cfg: BoxConfig, box: int = 0, device="cpu", w: torch.Tensor | None = None):
+    """A halo catalogue for the box: (positions (n_halo, 3) FP32 in [0, L),
+    masses (n_halo,) FP32), with host cells drawn with probability proportional
+    to the density w (generated when not given), uniform positions inside the
+    cell and masses from dN/dM ~ M^-1.9 on [m_lo, m_hi]."""
+    n = cfg.n
+    if w is None:
+        w = make_density(n, config_seed(cfg.index, box), device=device,
+                         dtype=torch.float64 if n <= 256 else torch.float32)
+    gen = _gen(device, config_seed(cfg.index, box) + 11)
+    cdf = torch.cumsum(w.reshape(-1).to(torch.float64), 0)
+    u = torch.rand(cfg.n_halo, generator=gen, device=device, dtype=torch.float64) * cdf[-1].item()
+    cell = torch.searchsorted(cdf, u).clamp_max(n * n * n - 1)
+    del cdf, u
+    cxyz = torch.stack([cell // (n * n), (cell // n) % n, cell % n], 1).to(torch.float64)
+    off = torch.rand((cfg.n_halo, 3), generator=gen, device=device, dtype=torch.float64)
+    pos = ((cxyz + off) * (cfg.box_len / n)).to(torch.float32)
+    pos = torch.where(pos >= cfg.box_len, torch.zeros_like(pos), pos)   # float rounding at the top edge
+    a, b = cfg.m_lo ** -0.9, cfg.m_hi ** -0.9
+    um = torch.rand(cfg.n_halo, generator=gen, device=device, dtype=torch.float64)
+    mass = ((a + um * (b - a)) ** (-1.0 / 0.9)).to(torch.float32)
+    return pos.contiguous(), mass.contiguous()
+
+
 def make_intensity(n: int, seed: int, device="cpu", ties: bool = True, negatives: bool = True) -> torch.Tensor:
     """A correlated FP32 intensity-like field for matching-only tests.
 

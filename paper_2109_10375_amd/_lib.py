@@ -24,8 +24,9 @@ SYMBOLS = [
     "amber_weibull_table", "amber_plan_create", "amber_plan_destroy", "amber_workspace_bytes",
     "amber_radiation", "amber_rank", "amber_zre", "amber_status", "amber_profile_begin",
     "amber_profile_end", "amber_batch_workspace_bytes", "amber_batch_run", "amber_spectra_workspace_bytes",
-    "amber_spectra", "amber_growth_table",
+    "amber_spectra", "amber_growth_table", "amber_halo_workspace_bytes", "amber_radiation_from_halos",
 ]
+ASSIGN_NGP, ASSIGN_CIC, ASSIGN_TSC = 1, 2, 3
 FIELD_RAW, FIELD_OVERDENSITY, FIELD_REDSHIFT = 0, 1, 2
 
 
@@ -81,6 +82,10 @@ def lib() -> ctypes.CDLL:
         L.amber_weibull_from_coeffs.argtypes = [d, d, d, ctypes.POINTER(AmberWeibull)]
         L.amber_weibull_table.argtypes = [ctypes.POINTER(AmberWeibull), vp, i64]
         L.amber_growth_table.argtypes = [ctypes.POINTER(AmberWeibull), d, d, vp, i64]
+        L.amber_halo_workspace_bytes.argtypes = [vp]
+        L.amber_halo_workspace_bytes.restype = sz
+        L.amber_radiation_from_halos.argtypes = [vp, vp, vp, i64, i, i, ctypes.POINTER(d), i, ctypes.POINTER(vp), vp,
+                                                 sz, vp]
         L.amber_plan_create.argtypes = [ctypes.POINTER(vp), i, d]
         L.amber_plan_destroy.argtypes = [vp]
         L.amber_plan_destroy.restype = None
@@ -218,6 +223,28 @@ class Plan:
         ws = self.workspace(len(l))
         _check(lib().amber_radiation(self._h, src, larr, len(l), ptrs, ctypes.c_void_p(ws.data_ptr()),
                                      ws.numel(), _stream()), "amber_radiation")
+        return list(out)
+
+    def radiation_from_halos(self, pos: torch.Tensor, mass: torch.Tensor, l_mfp: Sequence[float],
+                             scheme: int = ASSIGN_CIC, interlace: bool = True,
+                             out: Sequence[torch.Tensor] | None = None):
+        """amber_radiation_from_halos: J per mean free path from a halo
+        catalogue (positions (n_halo, 3) in [0, box_len), masses (n_halo,))."""
+        l = [float(x) for x in l_mfp]
+        nh = int(mass.numel())
+        if out is None:
+            out = [torch.empty((self.n,) * 3, dtype=torch.float32, device=self.device) for _ in l]
+        pp = _dev_ptr(pos, torch.float32, 3 * nh, "pos") if nh else None
+        pm = _dev_ptr(mass, torch.float32, nh, "mass") if nh else None
+        ptrs = (ctypes.c_void_p * len(l))(*[_dev_ptr(o, torch.float32, self.n3, "J").value for o in out])
+        larr = (ctypes.c_double * len(l))(*l)
+        need = int(lib().amber_halo_workspace_bytes(self._h))
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        _check(lib().amber_radiation_from_halos(self._h, pp, pm, nh, int(scheme), 1 if interlace else 0, larr, len(l),
+                                                ptrs, ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel(),
+                                                _stream()), "amber_radiation_from_halos")
         return list(out)
 
     def rank(self, J: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:

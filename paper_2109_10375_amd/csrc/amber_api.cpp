@@ -83,7 +83,7 @@ bool solve_c(double le, double lm, double ll, double az, double* c_out) {
 
 }  // namespace
 
-WsLayout ws_layout(int n, int n_lmfp) {
+WsLayout ws_layout(int n, int n_lmfp, bool halo_meshes) {
     WsLayout L{};
     const size_t N = (size_t)n, n3 = N * N * N;
     const size_t n_tiles = (n3 + 4095) / 4096;
@@ -101,6 +101,11 @@ WsLayout ws_layout(int n, int n_lmfp) {
     } else {
         L.spec_b = L.spec_a;
         L.nyq_b = L.nyq_a;
+    }
+    L.mesh[0] = L.mesh[1] = f;
+    if (halo_meshes) {
+        L.mesh[0] = f; f = align256(f + n3 * 4);
+        L.mesh[1] = f; f = align256(f + n3 * 4);
     }
     // ranking and matching (same region: the stages never overlap on a stream)
     size_t r = region;
@@ -337,6 +342,30 @@ int amber_radiation(amber_plan plan, const float* d_src, const double* l_mfp, in
     if (ws_bytes < L.total) return AMBER_E_WORKSPACE;
     return fft_radiation(plan, d_src, l_mfp, n_lmfp, d_J, static_cast<unsigned char*>(d_ws), L,
                          static_cast<hipStream_t>(stream));
+}
+
+size_t amber_halo_workspace_bytes(amber_plan plan) {
+    if (!plan) return 0;
+    return ws_layout(plan->n, 2, true).total;
+}
+
+int amber_radiation_from_halos(amber_plan plan, const float* d_pos, const float* d_mass, int64_t n_halo,
+                               int scheme, int interlace, const double* l_mfp, int n_lmfp, float* const* d_J,
+                               void* d_ws, size_t ws_bytes, void* stream) {
+    if (!plan || !l_mfp || !d_J || !d_ws || n_lmfp < 1 || n_lmfp > 64 || n_halo < 0) return AMBER_E_ARG;
+    if (n_halo > 0 && (!d_pos || !d_mass)) return AMBER_E_ARG;
+    if (n_halo > (int64_t)1 << 40 || scheme < 1 || scheme > 3 || (interlace != 0 && interlace != 1)) return AMBER_E_ARG;
+    for (int i = 0; i < n_lmfp; ++i)
+        if (!(l_mfp[i] > 0.0) || !std::isfinite(l_mfp[i]) || !d_J[i]) return AMBER_E_ARG;
+    const WsLayout L = ws_layout(plan->n, 2, true);
+    if (ws_bytes < L.total) return AMBER_E_WORKSPACE;
+    unsigned char* ws = static_cast<unsigned char*>(d_ws);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = halo_source_spectrum(plan, d_pos, d_mass, n_halo, scheme, interlace, ws, L, s);
+    if (rc != AMBER_OK) return rc;
+    return fft_from_spectrum(plan, reinterpret_cast<float2*>(ws + L.spec_a), reinterpret_cast<float2*>(ws + L.nyq_a),
+                             l_mfp, n_lmfp, d_J, reinterpret_cast<float2*>(ws + L.spec_b),
+                             reinterpret_cast<float2*>(ws + L.nyq_b), s);
 }
 
 int amber_rank(amber_plan plan, const float* d_J, uint32_t* d_perm, void* d_ws, size_t ws_bytes, void* stream) {

@@ -249,6 +249,7 @@ __device__ __forceinline__ int signed_freq(int m, int n) { return (2 * m <= n) ?
 
 // Column pass.  MODE 0: one transform (INV selects the direction).
 // MODE 1: forward transform, multiply by Khat(|k|)/N^3, inverse transform.
+// MODE 2: the input is already transformed along x: multiply, inverse.
 template <int N, int MODE, bool INV>
 __global__ __launch_bounds__(Shape<N>::C * Shape<N>::N1, 2) void k_fft_cols(
     const float2* __restrict__ in, float2* __restrict__ out, const float2* __restrict__ tw,
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(Shape<N>::C * Shape<N>::N1, 2) void k_fft_cols(
     if (MODE == 0) {
         fft_2step<N, N1, INV, 1, (N2 + 1) * C, C>(v, t, col, tw);
     } else {
-        fft_2step<N, N1, false, 1, (N2 + 1) * C, C>(v, t, col, tw);
+        if (MODE == 1) fft_2step<N, N1, false, 1, (N2 + 1) * C, C>(v, t, col, tw);
         int my, mz;
         if (m.nyq) {
             my = tb * C + c;
@@ -457,6 +458,58 @@ int fft_forward(const amber_plan_s* p, const float* d_src, float2* spec, float2*
         case 256: return run_forward<256>(p, d_src, spec, nyq, s);
         case 512: return run_forward<512>(p, d_src, spec, nyq, s);
         case 1024: return run_forward<1024>(p, d_src, spec, nyq, s);
+        default: return AMBER_E_SIZE;
+    }
+}
+
+// J_l from a spectrum already transformed along all three axes (main + Nyquist
+// plane): per l_mfp, multiply by Khat/N^3 and inverse x in one pass (into the
+// scratch spectrum when there are several l_mfp, in place otherwise), inverse y,
+// complex-to-real.
+template <int N>
+int run_from_spectrum(const amber_plan_s* p, float2* spec, float2* nyq, const double* l_mfp, int n_lmfp,
+                      float* const* d_J, float2* spec_tmp, float2* nyq_tmp, hipStream_t s) {
+    constexpr int H = N / 2, C = Shape<N>::C, N1 = Shape<N>::N1, ZL = Shape<N>::ZL, M1 = Shape<N>::M1;
+    const long long n_lines = (long long)N * N;
+    const float2* tw = p->d_tw;
+    const dim3 zblk(ZL * M1), cblk(C * N1);
+    const unsigned zgrid = (unsigned)((n_lines + ZL - 1) / ZL);
+    const ColGeom y_main{H, 1, (long long)N * H, C, H / C};
+    const ColGeom y_nyq{1, N, 0, (long long)C * N, N / C};
+    const ColGeom x_main{(long long)N * H, 1, H, C, H / C};
+    const ColGeom x_nyq{N, 1, 0, C, N / C};
+    const unsigned g_main = (unsigned)N * (H / C), g_nyq = (unsigned)(N / C);
+    const MulArgs none{0.f, 0.f, 0.f, 0};
+    for (int i = 0; i < n_lmfp; ++i) {
+        float2* so = (n_lmfp == 1) ? spec : spec_tmp;
+        float2* no = (n_lmfp == 1) ? nyq : nyq_tmp;
+        const float k0 = (float)(2.0 * kPi / p->box_len);
+        const float sc = (float)(1.0 / ((double)N * N * N));
+        const MulArgs mm{k0, (float)l_mfp[i], sc, 0};
+        const MulArgs mn{k0, (float)l_mfp[i], sc, 1};
+        AMBER_LAUNCH(p, "fft_x_mul_inv", (k_fft_cols<N, 2, false>), dim3(g_main), cblk, s, spec, so, tw, x_main, mm);
+        AMBER_LAUNCH(p, "fft_nyq_x_mul_inv", (k_fft_cols<N, 2, false>), dim3(g_nyq), cblk, s, nyq, no, tw, x_nyq, mn);
+        AMBER_LAUNCH(p, "fft_y_inv", (k_fft_cols<N, 0, true>), dim3(g_main), cblk, s, so, so, tw, y_main, none);
+        AMBER_LAUNCH(p, "fft_nyq_y_inv", (k_fft_cols<N, 0, true>), dim3(g_nyq), cblk, s, no, no, tw, y_nyq, none);
+        AMBER_LAUNCH(p, "fft_z_c2r", (k_fft_z_c2r<N>), dim3(zgrid), zblk, s, so, no, d_J[i], tw, n_lines);
+    }
+    AMBER_HIP_CHECK(hipGetLastError());
+    return AMBER_OK;
+}
+
+int fft_from_spectrum(const amber_plan_s* p, float2* spec, float2* nyq, const double* l_mfp, int n_lmfp,
+                      float* const* d_J, float2* spec_tmp, float2* nyq_tmp, hipStream_t s) {
+    switch (p->n) {
+        case 8: return run_from_spectrum<8>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
+        case 16: return run_from_spectrum<16>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
+        case 32: return run_from_spectrum<32>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
+        case 64: return run_from_spectrum<64>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
+        case 96: return run_from_spectrum<96>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
+        case 128: return run_from_spectrum<128>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
+        case 192: return run_from_spectrum<192>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
+        case 256: return run_from_spectrum<256>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
+        case 512: return run_from_spectrum<512>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
+        case 1024: return run_from_spectrum<1024>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
         default: return AMBER_E_SIZE;
     }
 }

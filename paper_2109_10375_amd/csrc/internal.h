@@ -58,6 +58,7 @@ struct WsLayout {
     size_t nyq_a;       // N x N complex Nyquist plane (kz = N/2)
     size_t spec_b;      // second spectrum (several l_mfp)
     size_t nyq_b;
+    size_t mesh[2];     // halo deposit meshes, N^3 FP32 each (halo sources only)
     size_t keys[2];     // sort keys (ping-pong), N^3 uint32
     size_t vals[2];     // cell indices, N^3 uint32
     size_t wts[2];      // weights carried with the keys, N^3 float
@@ -66,7 +67,7 @@ struct WsLayout {
     size_t total;
 };
 
-WsLayout ws_layout(int n, int n_lmfp);
+WsLayout ws_layout(int n, int n_lmfp, bool halo_meshes = false);
 
 // Words in each look-back region: 256 per 4096-cell tile, plus 256 tiles of
 // slack for partitions whose tiles do not straddle buckets.
@@ -131,6 +132,15 @@ int fft_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp
 
 // Forward transform only, into the given spectrum and Nyquist plane (fft.hip).
 int fft_forward(const amber_plan_s* p, const float* d_src, float2* spec, float2* nyq, hipStream_t s);
+
+// J_l = IDFT[spec Khat_l] / N^3 from a transformed spectrum (fft.hip); the
+// spectrum is kept when n_lmfp > 1 (the products go through spec_tmp).
+int fft_from_spectrum(const amber_plan_s* p, float2* spec, float2* nyq, const double* l_mfp, int n_lmfp,
+                      float* const* d_J, float2* spec_tmp, float2* nyq_tmp, hipStream_t s);
+
+// Halo catalogue -> interlaced, deconvolved source spectrum in spec_a (halos.hip).
+int halo_source_spectrum(const amber_plan_s* p, const float* d_pos, const float* d_mass, long long n_halo,
+                         int scheme, int interlace, unsigned char* ws, const WsLayout& L, hipStream_t s);
 
 // Shell-binned spectra of two forward transforms (spectra.hip).
 int spectra_bins(const amber_plan_s* p, const float2* spec_a, const float2* nyq_a, int kind_a,

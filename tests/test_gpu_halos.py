@@ -1,0 +1,98 @@
+"""Radiation fields from halo catalogues on the GPU (amber_radiation_from_halos:
+Sec. 3.2.1 Eqs. interlace, Wofk and Sec. 3.4.1) against the FP64 oracle.
+
+The deposit uses FP32 atomics, so J is compared with a tolerance: relative L2
+<= 1e-5 and every cell within 2e-5 max|J| (FP32 sums of a few masses per cell
+add ~1e-7 to the FFT's error).  At 1024^3 the oracle cannot run: sampled DFT
+modes of J are compared with the deposits of torch's own CIC (the input
+generator's, independent of the library) combined by Eq. interlace and Wofk.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def amber():
+    import paper_2109_10375_amd as amber
+    assert torch.cuda.is_available()
+    amber.lib()
+    return amber
+
+
+@pytest.mark.parametrize("n,scheme,inter", [(16, 1, False), (32, 2, False), (32, 2, True), (64, 3, True),
+                                            (96, 2, True), (64, 1, True)])
+def test_halo_radiation_vs_oracle(amber, n, scheme, inter):
+    cfg = inputs.BoxConfig("hal", n, 1.5625 * n, max(2000, n ** 3 // 20), 1e9, 1e12, index=800 + n)
+    pos, mass = inputs.make_halos(cfg)
+    l = 3.0
+    plan = amber.Plan(n, cfg.box_len)
+    (J,) = plan.radiation_from_halos(pos.cuda(), mass.cuda(), [l], scheme=scheme, interlace=inter)
+    torch.cuda.synchronize()
+    ref = oracle.radiation_from_halos(n, cfg.box_len, pos.numpy(), mass.numpy(), scheme, inter, l)
+    Jg = J.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(Jg - ref) / np.linalg.norm(ref)
+    mx = np.max(np.abs(Jg - ref)) / np.max(np.abs(ref))
+    print(f"halos n={n} p={scheme} interlace={inter}: relL2={rel:.2e} max={mx:.2e}", flush=True)
+    assert rel <= 1e-5 and mx <= 2e-5
+
+
+def test_several_lmfp_and_sum_rule(amber):
+    n = 32
+    cfg = inputs.BoxConfig("hal", n, 50.0, 3000, 1e9, 1e12, index=850)
+    pos, mass = inputs.make_halos(cfg)
+    ls = [0.5, 3.0, 20.0]
+    plan = amber.Plan(n, cfg.box_len)
+    Js = plan.radiation_from_halos(pos.cuda(), mass.cuda(), ls)
+    torch.cuda.synchronize()
+    msum = float(mass.to(torch.float64).sum())
+    for J, l in zip(Js, ls):
+        ref = oracle.radiation_from_halos(n, cfg.box_len, pos.numpy(), mass.numpy(), 2, True, l)
+        rel = np.linalg.norm(J.cpu().numpy() - ref) / np.linalg.norm(ref)
+        assert rel <= 1e-5
+        assert float(J.to(torch.float64).sum()) == pytest.approx(l * msum, rel=1e-5)
+
+
+def test_full_size_sampled_modes(amber):
+    cfg = inputs.CONFIGS["H"]
+    n, L, l = cfg.n, cfg.box_len, 3.0
+    dev = torch.device("cuda", 0)
+    print("generating the 1024^3 halo catalogue", flush=True)
+    pos, mass = inputs.make_halos(cfg, device=dev)
+    plan = amber.Plan(n, L)
+    (J,) = plan.radiation_from_halos(pos, mass, [l], scheme=2, interlace=True)
+    torch.cuda.synchronize()
+    msum = float(mass.to(torch.float64).sum())
+    assert float(J.to(torch.float64).sum()) == pytest.approx(l * msum, rel=1e-4)
+    Jh = J.cpu().numpy()
+    del J, plan
+    torch.cuda.empty_cache()
+    # torch CIC deposits of the same catalogue: as given and shifted by half a cell
+    from inputs.synth import _cic_deposit
+    cells = pos.to(torch.float64) * (n / L)
+    A = _cic_deposit(n, cells, mass.to(torch.float64), torch.float32).cpu().numpy()
+    B = _cic_deposit(n, cells + 0.5, mass.to(torch.float64), torch.float32).cpu().numpy()
+    del cells
+    jnorm = float(np.sqrt(np.sum(Jh.astype(np.float64) ** 2)))
+    k0 = 2 * math.pi / L
+    for m in [(0, 0, 0), (1, 0, 0), (3, 5, 7), (17, 200, 400), (511, 2, 100), (1000, 900, 33)]:
+        s = [x if 2 * x <= n else x - n for x in m]
+        W = 1.0
+        for sd in s:
+            a = math.pi * sd / n
+            W *= (math.sin(a) / a) ** 2 if sd else 1.0
+        theta = math.pi * sum(s) / n
+        Am, Bm = oracle.dft_coeff(A, m), oracle.dft_coeff(B, m)
+        Sm = (Am + complex(math.cos(theta), math.sin(theta)) * Bm) / (2 * W)
+        expect = Sm * oracle.kernel_hat(k0 * math.sqrt(sum(x * x for x in s)), l)
+        got = oracle.dft_coeff(Jh, m)
+        print(f"mode {m}: |DFT(J)| {abs(got):.4e} expected {abs(expect):.4e}", flush=True)
+        # the FP32 meshes of both sides add ~1e-7 relative per cell
+        assert abs(got - expect) <= 1e-5 * (abs(expect) + jnorm), m
