@@ -59,6 +59,8 @@ struct WsLayout {
     size_t spec_b;      // second spectrum (several l_mfp)
     size_t nyq_b;
     size_t mesh[2];     // halo deposit meshes, N^3 FP32 each (halo sources only)
+    size_t bins;        // halo tile bins: mass bound, counts, cursors, starts (+1), gate, scale (halo sources only)
+    size_t halo_tab;    // per-axis window and phase factors, N double4 (halo sources only)
     size_t keys[2];     // sort keys (ping-pong), N^3 uint32
     size_t vals[2];     // cell indices, N^3 uint32
     size_t wts[2];      // weights carried with the keys, N^3 float
@@ -137,6 +139,14 @@ int fft_forward(const amber_plan_s* p, const float* d_src, float2* spec, float2*
 // spectrum is kept when n_lmfp > 1 (the products go through spec_tmp).
 int fft_from_spectrum(const amber_plan_s* p, float2* spec, float2* nyq, const double* l_mfp, int n_lmfp,
                       float* const* d_J, float2* spec_tmp, float2* nyq_tmp, hipStream_t s);
+
+// Edge of the cubic mesh tiles the halo deposit bins by; grids it does not
+// divide use the direct (atomic) deposit.
+constexpr int kHaloTile = 16;
+inline size_t halo_tiles(int n) {
+    const size_t t = (n % kHaloTile == 0) ? (size_t)(n / kHaloTile) : 0;
+    return t * t * t;
+}
 
 // Halo catalogue -> interlaced, deconvolved source spectrum in spec_a (halos.hip).
 int halo_source_spectrum(const amber_plan_s* p, const float* d_pos, const float* d_mass, long long n_halo,
