@@ -247,6 +247,15 @@ struct MulArgs {
 
 __device__ __forceinline__ int signed_freq(int m, int n) { return (2 * m <= n) ? m : m - n; }
 
+// Workgroups are dispatched to the 8 XCDs round robin (block b runs on XCD
+// b % 8, each XCD with its own L2).  Neighbouring tiles read the two 64-byte
+// halves of the same 128-byte lines, so each XCD takes one contiguous run of
+// tiles instead of every eighth tile.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned grid) {
+    if (grid % 8u != 0u) return b;
+    return (b % 8u) * (grid / 8u) + b / 8u;
+}
+
 // Column pass.  MODE 0: one transform (INV selects the direction).
 // MODE 1: forward transform, multiply by Khat(|k|)/N^3, inverse transform.
 // MODE 2: the input is already transformed along x: multiply, inverse.
@@ -258,7 +267,8 @@ __global__ __launch_bounds__(Shape<N>::C * Shape<N>::N1, 2) void k_fft_cols(
     __shared__ float2 lds[N1 * (N2 + 1) * C];
     const int tid = threadIdx.x;
     const int c = tid % C, t = tid / C;
-    const int tb = blockIdx.x % g.tiles_b, ta = blockIdx.x / g.tiles_b;
+    const unsigned bid = xcd_tile(blockIdx.x, gridDim.x);
+    const int tb = bid % g.tiles_b, ta = bid / g.tiles_b;
     const long long base = (long long)ta * g.sa + (long long)tb * g.sb + (long long)c * g.col;
     float2 v[N2];
 #pragma unroll
@@ -289,106 +299,6 @@ __global__ __launch_bounds__(Shape<N>::C * Shape<N>::N1, 2) void k_fft_cols(
     }
 #pragma unroll
     for (int j = 0; j < N2; ++j) out[base + (long long)(t + N1 * j) * g.row] = v[j];
-}
-
-// Fused x pass at N = 1024 with 16 values per thread (the generic pass needs
-// 32, which leaves two waves per SIMD and spills): 64 threads per column, 8
-// columns per block.  The forward transform takes three register stages,
-// 1024 = 16 x 16 x 4, with n = t + 64 j and k = k1 + 16 q + 256 r, q = 4 s + u:
-//   stage 1 (thread t):          A[t][k1] = W_1024^(t k1) sum_j x[t + 64 j] W_16^(j k1)
-//   stage 2 (thread t = 4 k1 + p): B[k1][p][q] = W_64^(p q) sum_m A[p + 4 m][k1] W_16^(m q)
-//   stage 3 (thread t = 4 k1 + u): X[k1 + 16 q + 256 r] = sum_p B[k1][p][q] W_4^(p r)
-// with an LDS exchange between stages, so the spectrum ends up scattered over
-// the threads in a known order.  After the multiply by Khat/N^3 the inverse
-// runs the conjugate stages in reverse order and lands every value back where
-// it was loaded, so loads and stores use the same coalesced pattern.
-__global__ __launch_bounds__(512, 2) void k_fft_x1024(const float2* __restrict__ in, float2* __restrict__ out,
-                                                      const float2* __restrict__ tw, ColGeom g, MulArgs m) {
-    constexpr int N = 1024, C = 8, R = 16, P = R + 1;  // P: padded LDS row of 16 values
-    __shared__ float2 lds[64 * P * C];
-    const int tid = threadIdx.x;
-    const int c = tid % C, t = tid / C;
-    const int k1 = t >> 2, pu = t & 3;  // stage 2 and 3 roles of thread t
-    const int tb = blockIdx.x % g.tiles_b, ta = blockIdx.x / g.tiles_b;
-    const long long base = (long long)ta * g.sa + (long long)tb * g.sb + (long long)c * g.col;
-    float2* col = lds + c;
-    float2 v[R];
-#pragma unroll
-    for (int j = 0; j < R; ++j) v[j] = in[base + (long long)(t + 64 * j) * g.row];
-
-    // stage 1
-    Dft<R, false>::run(v);
-#pragma unroll
-    for (int e = 1; e < R; ++e) v[e] = cmul(v[e], tw[t * e]);
-#pragma unroll
-    for (int e = 0; e < R; ++e) col[(t * P + e) * C] = v[e];
-    __syncthreads();
-    // stage 2
-#pragma unroll
-    for (int mm = 0; mm < R; ++mm) v[mm] = col[((pu + 4 * mm) * P + k1) * C];
-    Dft<R, false>::run(v);
-#pragma unroll
-    for (int q = 1; q < R; ++q) v[q] = cmul(v[q], tw[16 * pu * q]);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < R; ++q) col[(t * P + q) * C] = v[q];
-    __syncthreads();
-    // stage 3: v[4 s + p] = B[k1][p][4 s + u], then X at k1 + 16 (4 s + u) + 256 r in v[4 s + r]
-#pragma unroll
-    for (int sg = 0; sg < 4; ++sg)
-#pragma unroll
-        for (int pp = 0; pp < 4; ++pp) v[4 * sg + pp] = col[((4 * k1 + pp) * P + 4 * sg + pu) * C];
-#pragma unroll
-    for (int sg = 0; sg < 4; ++sg) Dft<4, false>::run(v + 4 * sg);
-
-    // multiply by Khat(|k|)/N^3
-    int my, mz;
-    if (m.nyq) {
-        my = tb * C + c;
-        mz = N / 2;
-    } else {
-        my = ta;
-        mz = tb * C + c;
-    }
-    const int sy = signed_freq(my, N), sz = mz;
-    const int s2yz = sy * sy + sz * sz;
-#pragma unroll
-    for (int sg = 0; sg < 4; ++sg)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int sx = signed_freq(k1 + 64 * sg + 16 * pu + 256 * r, N);
-            const float kk = m.k0 * sqrtf((float)(sx * sx + s2yz));
-            const float K = (kk > 0.0f) ? atanf(kk * m.lmfp) / kk : m.lmfp;
-            v[4 * sg + r] = cscale(v[4 * sg + r], K * m.scale);
-        }
-
-    // inverse: stage 3, 2, 1 conjugated, in reverse
-#pragma unroll
-    for (int sg = 0; sg < 4; ++sg) Dft<4, true>::run(v + 4 * sg);
-    __syncthreads();
-#pragma unroll
-    for (int sg = 0; sg < 4; ++sg)
-#pragma unroll
-        for (int pp = 0; pp < 4; ++pp) col[((4 * k1 + pp) * P + 4 * sg + pu) * C] = v[4 * sg + pp];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < R; ++q) v[q] = col[(t * P + q) * C];
-    // conjugate twiddles as W^(N - e): other table entries, so the compiler
-    // does not keep the forward ones live across the whole kernel
-#pragma unroll
-    for (int q = 1; q < R; ++q) v[q] = cmul(v[q], tw[(N - 16 * pu * q) & (N - 1)]);
-    Dft<R, true>::run(v);
-    __syncthreads();
-#pragma unroll
-    for (int mm = 0; mm < R; ++mm) col[((pu + 4 * mm) * P + k1) * C] = v[mm];
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < R; ++e) v[e] = col[(t * P + e) * C];
-#pragma unroll
-    for (int e = 1; e < R; ++e) v[e] = cmul(v[e], tw[(N - t * e) & (N - 1)]);
-    Dft<R, true>::run(v);
-#pragma unroll
-    for (int j = 0; j < R; ++j) out[base + (long long)(t + 64 * j) * g.row] = v[j];
 }
 
 // z pass, real to complex: N reals per line -> N/2 + 1 complex (N/2 in main,
@@ -511,15 +421,8 @@ int run_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp
         const float sc = (float)(1.0 / ((double)N * N * N));
         const MulArgs mm{k0, (float)l_mfp[i], sc, 0};
         const MulArgs mn{k0, (float)l_mfp[i], sc, 1};
-        if constexpr (N == 1024) {
-            static_assert(C == 8, "k_fft_x1024 takes tiles of 8 columns");
-            AMBER_LAUNCH(p, "fft_x_mul", k_fft_x1024, dim3(g_main), dim3(512), s, spec_a, so, tw, x_main, mm);
-            AMBER_LAUNCH(p, "fft_nyq_x_mul", k_fft_x1024, dim3(g_nyq), dim3(512), s, nyq_a, no, tw, x_nyq, mn);
-        } else {
-            AMBER_LAUNCH(p, "fft_x_mul", (k_fft_cols<N, 1, false>), dim3(g_main), cblk, s, spec_a, so, tw, x_main, mm);
-            AMBER_LAUNCH(p, "fft_nyq_x_mul", (k_fft_cols<N, 1, false>), dim3(g_nyq), cblk, s, nyq_a, no, tw, x_nyq,
-                         mn);
-        }
+        AMBER_LAUNCH(p, "fft_x_mul", (k_fft_cols<N, 1, false>), dim3(g_main), cblk, s, spec_a, so, tw, x_main, mm);
+        AMBER_LAUNCH(p, "fft_nyq_x_mul", (k_fft_cols<N, 1, false>), dim3(g_nyq), cblk, s, nyq_a, no, tw, x_nyq, mn);
         AMBER_LAUNCH(p, "fft_y_inv", (k_fft_cols<N, 0, true>), dim3(g_main), cblk, s, so, so, tw, y_main, none);
         AMBER_LAUNCH(p, "fft_nyq_y_inv", (k_fft_cols<N, 0, true>), dim3(g_nyq), cblk, s, no, no, tw, y_nyq, none);
         AMBER_LAUNCH(p, "fft_z_c2r", (k_fft_z_c2r<N>), dim3(zgrid), zblk, s, so, no, d_J[i], tw, n_lines);

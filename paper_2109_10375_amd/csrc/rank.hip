@@ -102,18 +102,18 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const float* __restrict__
                     atomicAdd(&h[wave][2][(key >> 16) & 255u], 1u);
                 }
                 // The top digit (sign and exponent) takes few values among
-                // neighbouring cells: the lanes sharing it find each other with
-                // 8 ballots and the lowest of them adds the count once.
+                // neighbouring cells: one count per distinct value in the
+                // wave, each added once by the lowest lane holding it.
                 const unsigned d3 = key >> 24;
-                unsigned long long peers = __ballot(live);
-#pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    const unsigned long long m = __ballot((d3 >> b) & 1u);
-                    peers &= ((d3 >> b) & 1u) ? m : ~m;
-                }
                 const int lane = threadIdx.x & 63;
-                if (live && (peers & ((1ull << lane) - 1ull)) == 0ull)
-                    atomicAdd(&h[wave][3][d3], (unsigned)__popcll(peers));
+                unsigned long long left = __ballot(live);
+                while (left) {  // wave-uniform: one round per distinct digit
+                    const int leader = __ffsll((long long)left) - 1;
+                    const unsigned dv = __builtin_amdgcn_readlane(d3, leader);
+                    const unsigned long long same = __ballot(live && d3 == dv);
+                    if (lane == leader) atomicAdd(&h[wave][3][dv], (unsigned)__popcll(same));
+                    left &= ~same;
+                }
             }
         }
     }
