@@ -523,6 +523,30 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
     const double unit = ldexp(1.0, -qmin);  // one cell in the units of the exact sums
     const double ns = (double)n * unit;
     auto z_of = [&](const HistArg& H, long long gl, const double* x, float* zf) {
+#pragma clang fp contract(off)
+        // The middle rank's bracket and interpolation constants, once per
+        // thread: a rank with X_jm >= F > X_jm+1 has exactly this bracket
+        // (X is non-increasing), so only its own t needs computing.
+        double xm0 = 0.0, xm1 = 0.0, zm = 0.0, denm = 0.0, dzm = 0.0;
+        if (!H.G) {
+            const double fm = __ddiv_rn(cn[kPer / 2], tot);
+            int km = 0;
+#pragma unroll
+            for (int e = 1; e < 7; ++e) km += (x[e] >= fm) ? 1 : 0;
+            xm0 = x[0];
+            xm1 = x[1];
+#pragma unroll
+            for (int e = 1; e < 7; ++e)
+                if (km == e) {
+                    xm0 = x[e];
+                    xm1 = x[e + 1];
+                }
+            const long long jm = gl + km;
+            zm = H.a + (double)jm * H.h;
+            const double zm1 = H.a + (double)(jm + 1) * H.h;
+            denm = xm0 - xm1;
+            dzm = zm1 - zm;
+        }
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             const double f = __ddiv_rn(cn[j], tot);  // F_n = RN(C_n) / RN(C_N)
@@ -531,6 +555,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
                 if (H.G) {
                     const double ks = (double)(p0 + j + 1) * unit;
                     z = invert_growth(ks, ns, cn[j], tot, H.a, H.h, H.T, H.z_top, H.X, H.G);
+                } else if (xm0 >= f && xm1 < f) {  // the same operations as interpolate_xy
+                    const double t = (denm != 0.0) ? (xm0 - f) / denm : 0.0;
+                    z = zm + t * dzm;
+                    z = (z < H.z_top) ? z : H.z_top;
                 } else if (x[0] >= f && x[7] < f) {
                     int kk = 0;
 #pragma unroll
