@@ -411,7 +411,7 @@ __global__ __launch_bounds__(kPrefixThreads) void k_block_prefix(u128* __restric
 // The launch runs the 64-bit variant when the exact total fits in 64 bits and
 // the 128-bit one otherwise (the other variant's blocks return at once).
 // fill[b] (cleared before the launch) counts the slots of bucket b handed out.
-template <int NH, bool WIDE>
+template <int NH, bool WIDE, bool GROWTH>
 __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
     const unsigned* __restrict__ perm, const float* __restrict__ w_sorted, long long n, Ctrl* ctrl,
     const u128* __restrict__ local, const u128* __restrict__ block_excl, unsigned* __restrict__ fill,
@@ -524,6 +524,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
     const double ns = (double)n * unit;
     auto z_of = [&](const HistArg& H, long long gl, const double* x, float* zf) {
 #pragma clang fp contract(off)
+        if constexpr (GROWTH) {
+            if (H.G) {
+#pragma unroll
+                for (int j = 0; j < kPer; ++j) {
+                    const double ks = (double)(p0 + j + 1) * unit;
+                    zf[j] = pos[j] != 0xffffffffu
+                                ? (float)invert_growth(ks, ns, cn[j], tot, H.a, H.h, H.T, H.z_top, H.X, H.G)
+                                : 0.0f;
+                }
+                return;
+            }
+        }
         // The middle rank's bracket and interpolation constants, once per
         // thread: a rank with X_jm >= F > X_jm+1 has exactly this bracket
         // (X is non-increasing), so only its own t needs computing.
@@ -552,10 +564,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
             const double f = __ddiv_rn(cn[j], tot);  // F_n = RN(C_n) / RN(C_N)
             double z = 0.0;
             if (pos[j] != 0xffffffffu) {
-                if (H.G) {
-                    const double ks = (double)(p0 + j + 1) * unit;
-                    z = invert_growth(ks, ns, cn[j], tot, H.a, H.h, H.T, H.z_top, H.X, H.G);
-                } else if (xm0 >= f && xm1 < f) {  // the same operations as interpolate_xy
+                if (xm0 >= f && xm1 < f) {  // the same operations as interpolate_xy
                     const double t = (denm != 0.0) ? (xm0 - f) / denm : 0.0;
                     z = zm + t * dzm;
                     z = (z < H.z_top) ? z : H.z_top;
@@ -819,15 +828,20 @@ int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, flo
                               w.d_growth, d_zre[h0 + i]};
         }
         if (g > 0) AMBER_LAUNCH(p, "match_clear", k_clear, dim3(1), dim3(256), s, fill1, kL1);
-#define AMBER_SCAN(NHV)                                                                                      \
-    AMBER_LAUNCH(p, "match_scan_partition", (k_scan_partition<NHV, false>), grid, blk, s, perm, w_sorted, n, \
-                 ctrl, local, block_excl, fill1, sum_tpb, S1, rinv, hs, p1_idx, p1_z[0], p1_z[1], p1_z[2]);  \
-    AMBER_LAUNCH(p, "match_scan_partition_wide", (k_scan_partition<NHV, true>), grid, blk, s, perm, w_sorted, \
+        bool growth = false;  // the growth inversion lives in its own kernels (it needs more registers)
+        for (int i = 0; i < hs.n; ++i) growth |= hs.h[i].G != nullptr;
+#define AMBER_SCAN(NHV, GR)                                                                                       \
+    AMBER_LAUNCH(p, "match_scan_partition", (k_scan_partition<NHV, false, GR>), grid, blk, s, perm, w_sorted, n,  \
+                 ctrl, local, block_excl, fill1, sum_tpb, S1, rinv, hs, p1_idx, p1_z[0], p1_z[1], p1_z[2]);       \
+    AMBER_LAUNCH(p, "match_scan_partition_wide", (k_scan_partition<NHV, true, GR>), grid, blk, s, perm, w_sorted, \
                  n, ctrl, local, block_excl, fill1, sum_tpb, S1, rinv, hs, p1_idx, p1_z[0], p1_z[1], p1_z[2]);
-        switch (hs.n) {
-            case 1: AMBER_SCAN(1) break;
-            case 2: AMBER_SCAN(2) break;
-            default: AMBER_SCAN(3) break;
+        switch (hs.n + (growth ? 3 : 0)) {
+            case 1: AMBER_SCAN(1, false) break;
+            case 2: AMBER_SCAN(2, false) break;
+            case 3: AMBER_SCAN(3, false) break;
+            case 4: AMBER_SCAN(1, true) break;
+            case 5: AMBER_SCAN(2, true) break;
+            default: AMBER_SCAN(3, true) break;
         }
 #undef AMBER_SCAN
         for (int i = 0; i < hs.n; ++i) {
