@@ -102,18 +102,23 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const float* __restrict__
                     atomicAdd(&h[wave][2][(key >> 16) & 255u], 1u);
                 }
                 // The top digit (sign and exponent) takes few values among
-                // neighbouring cells: one count per distinct value in the
-                // wave, each added once by the lowest lane holding it.
+                // neighbouring cells: the two most common ones in the wave
+                // (in practice) are counted once each by the lowest lane
+                // holding them, any other lane adds its own.
                 const unsigned d3 = key >> 24;
                 const int lane = threadIdx.x & 63;
                 unsigned long long left = __ballot(live);
-                while (left) {  // wave-uniform: one round per distinct digit
-                    const int leader = __ffsll((long long)left) - 1;
-                    const unsigned dv = __builtin_amdgcn_readlane(d3, leader);
-                    const unsigned long long same = __ballot(live && d3 == dv);
-                    if (lane == leader) atomicAdd(&h[wave][3][dv], (unsigned)__popcll(same));
-                    left &= ~same;
+#pragma unroll
+                for (int round = 0; round < 2; ++round) {
+                    if (left) {  // wave-uniform
+                        const int leader = __ffsll((long long)left) - 1;
+                        const unsigned dv = __builtin_amdgcn_readlane(d3, leader);
+                        const unsigned long long same = __ballot(live && d3 == dv);
+                        if (lane == leader) atomicAdd(&h[wave][3][dv], (unsigned)__popcll(same));
+                        left &= ~same;
+                    }
                 }
+                if ((left >> lane) & 1ull) atomicAdd(&h[wave][3][d3], 1u);
             }
         }
     }
