@@ -297,8 +297,12 @@ __global__ __launch_bounds__(Shape<N>::C * Shape<N>::N1, 2) void k_fft_cols(
         }
         fft_2step<N, N1, true, 1, (N2 + 1) * C, C>(v, t, col, tw);
     }
+    // The store addresses are recomputed here rather than kept from the loads
+    // (kept, they are spilled to scratch in the fused passes at N = 1024).
+    long long obase = base + (long long)t * g.row;
+    asm volatile("" : "+v"(obase));
 #pragma unroll
-    for (int j = 0; j < N2; ++j) out[base + (long long)(t + N1 * j) * g.row] = v[j];
+    for (int j = 0; j < N2; ++j) out[obase + (long long)(N1 * j) * g.row] = v[j];
 }
 
 // z pass, real to complex: N reals per line -> N/2 + 1 complex (N/2 in main,
