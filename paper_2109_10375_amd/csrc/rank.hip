@@ -251,12 +251,18 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     for (int j = 0; j < kKeysPerThread; ++j) {
         const bool ok = (wbase + 64 * j + lane) < n;
         const unsigned d = (key[j] >> shift) & 255u;
-        unsigned long long peers = __ballot(ok);
+        const unsigned long long ok_mask = __ballot(ok);
+        // lanes whose digit equals this lane's, bit by bit on 32-bit halves
+        // (each step is one 3-input bit operation per half)
+        unsigned plo = (unsigned)ok_mask, phi = (unsigned)(ok_mask >> 32);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            const unsigned long long m = __ballot((d >> b) & 1u);
-            peers &= ((d >> b) & 1u) ? m : ~m;
+            const unsigned ext = 0u - ((d >> b) & 1u);  // all ones where the bit is set
+            const unsigned long long m = __ballot(ext != 0u);
+            plo &= ~(ext ^ (unsigned)m);
+            phi &= ~(ext ^ (unsigned)(m >> 32));
         }
+        const unsigned long long peers = ((unsigned long long)phi << 32) | plo;
         unsigned r = 0;
         if (ok) {
             const unsigned before = (unsigned)__popcll(peers & lt);
