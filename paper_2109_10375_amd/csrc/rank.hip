@@ -216,20 +216,39 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     bool bad_w = false;
     int qmin = 0x7fffffff;
     const long long wbase = tile_base + (long long)wave * (64 * kKeysPerThread);
-    // All loads first, from clamped positions (no branch around a load, so
-    // they are all in flight together); out-of-range lanes are masked after.
+    // All loads first (no branch around a load, so they are all in flight
+    // together).  Element indices fit in 32 bits (n <= 2^30): a full tile
+    // loads at one lane offset plus constant strides; the last tile clamps
+    // its positions, and its out-of-range lanes are masked after.
+    const unsigned lane0 = (unsigned)wbase + (unsigned)lane;
+    if (tile_base + kTile <= n) {
 #pragma unroll
-    for (int j = 0; j < kKeysPerThread; ++j) {
-        const long long pos = wbase + 64 * j + lane;
-        const long long pc = pos < n ? pos : n - 1;
-        if (FIRST) {
-            key[j] = __float_as_uint(J[pc]);
-            val[j] = (unsigned)pos;
-        } else {
-            key[j] = keys_in[pc];
-            val[j] = vals_in[pc];
+        for (int j = 0; j < kKeysPerThread; ++j) {
+            const unsigned pos = lane0 + 64u * j;
+            if (FIRST) {
+                key[j] = __float_as_uint(J[pos]);
+                val[j] = pos;
+            } else {
+                key[j] = keys_in[pos];
+                val[j] = vals_in[pos];
+            }
+            if (CARRY) wt[j] = w_in[pos];
         }
-        if (CARRY) wt[j] = w_in[pc];
+    } else {
+        const unsigned last = (unsigned)(n - 1);
+#pragma unroll
+        for (int j = 0; j < kKeysPerThread; ++j) {
+            const unsigned pos = lane0 + 64u * j;
+            const unsigned pc = pos < last ? pos : last;
+            if (FIRST) {
+                key[j] = __float_as_uint(J[pc]);
+                val[j] = pos;
+            } else {
+                key[j] = keys_in[pc];
+                val[j] = vals_in[pc];
+            }
+            if (CARRY) wt[j] = w_in[pc];
+        }
     }
 #pragma unroll
     for (int j = 0; j < kKeysPerThread; ++j) {
