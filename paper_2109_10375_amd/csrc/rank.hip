@@ -366,9 +366,9 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
         if (i < valid) {
             const unsigned kk = stage[i];
             const unsigned dd = (kk >> shift) & 255u;
-            const long long t = (long long)gbase[dd] + (i - (int)loff[dd]);
-            if (t >= 0 && t < n) {
-                dst[k] = (unsigned)t;
+            const unsigned t = gbase[dd] + ((unsigned)i - loff[dd]);  // i >= loff[dd] inside the digit's run
+            if (t < (unsigned)n) {
+                dst[k] = t;
                 if (!LAST) keys_out[t] = kk;
             }
         }
