@@ -664,25 +664,29 @@ __global__ __launch_bounds__(kPartThreads) void k_partition2(const unsigned* __r
     __syncthreads();
     const unsigned tile = blockIdx.x;  // no waits on other tiles
     const unsigned b = tile / tiles_per_bucket, k = tile % tiles_per_bucket;
-    const long long bstart = (long long)b * S1;
-    const long long t0 = bstart + (long long)k * kPartTile;
-    const long long t1 = t0 + kPartTile < bstart + S1 ? t0 + kPartTile : bstart + S1;
+    // cell and pair indices fit in 32 bits (n <= 2^30)
+    const unsigned bstart = b * S1;
+    const unsigned t0 = bstart + k * (unsigned)kPartTile;
+    const unsigned t1 = t0 + kPartTile < bstart + S1 ? t0 + kPartTile : bstart + S1;
     const int valid = (int)(t1 - t0);
     unsigned idx[kPer], rb[kPer];
     float z[kPer];
+    // every load in flight before any is used: no branch around a load (the
+    // last tile of a bucket clamps its positions instead)
+    const unsigned lastv = (unsigned)valid - 1u;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
-        const int i = j * kPartThreads + tid;
-        const bool ok = i < valid;
-        idx[j] = ok ? in_idx[t0 + i] : 0u;
-        z[j] = ok ? in_z[t0 + i] : 0.0f;
+        const unsigned i = (unsigned)(j * kPartThreads + tid);
+        const unsigned at = t0 + (valid == kPartTile ? i : (i < lastv ? i : lastv));
+        idx[j] = in_idx[at];
+        z[j] = in_z[at];
     }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int i = j * kPartThreads + tid;
-        const long long rel = (long long)idx[j] - bstart;
-        const bool live = i < valid && rel >= 0 && rel < (long long)S1;
-        const unsigned sb = live ? div_exact((unsigned)rel, S2, s2_rinv) : 0u;
+        const unsigned rel = idx[j] - bstart;  // wraps above S1 when idx < bstart
+        const bool live = i < valid && rel < S1;
+        const unsigned sb = live ? div_exact(rel, S2, s2_rinv) : 0u;
         rb[j] = live ? (sb << 16) | atomicAdd(&lcnt[sb], 1u) : 0xffffffffu;
     }
     __syncthreads();
@@ -694,7 +698,7 @@ __global__ __launch_bounds__(kPartThreads) void k_partition2(const unsigned* __r
     const unsigned lo = bucket_excl_scan<kL2>(cnt, scan_sh);
     if (tid < kL2) {
         loff[tid] = lo;
-        gbase[tid] = (unsigned)(bstart + (long long)tid * S2 + slot0);
+        gbase[tid] = bstart + (unsigned)tid * S2 + slot0;
     }
     __syncthreads();
     unsigned pos[kPer];
@@ -712,12 +716,12 @@ __global__ __launch_bounds__(kPartThreads) void k_partition2(const unsigned* __r
         dst[kk] = 0xffffffffu;
         if (i < valid) {
             const unsigned c = stage[i];
-            const long long rel = (long long)c - bstart;
-            if (rel >= 0 && rel < (long long)S1) {
-                const unsigned s2 = div_exact((unsigned)rel, S2, s2_rinv);
-                const long long t = (long long)gbase[s2] + (i - (int)loff[s2]);
-                if (t >= 0 && t < n) {
-                    dst[kk] = (unsigned)t;
+            const unsigned rel = c - bstart;
+            if (rel < S1) {
+                const unsigned s2 = div_exact(rel, S2, s2_rinv);
+                const unsigned t = gbase[s2] + ((unsigned)i - loff[s2]);
+                if (t < (unsigned)n) {
+                    dst[kk] = t;
                     out_idx[t] = c;
                 }
             }
