@@ -607,11 +607,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
         dst[k] = 0xffffffffu;
         if (i < valid) {
             const unsigned c = stage[i];
-            if (c < (unsigned long long)n) {
+            if (c < (unsigned)n) {  // indices fit in 32 bits (n <= 2^30)
                 const unsigned b = div_exact(c, bucket_size, bucket_rinv);
-                const long long t = (long long)gbase[b] + (i - (int)loff[b]);
-                if (t >= 0 && t < n) {  // always, for consistent counts
-                    dst[k] = (unsigned)t;
+                const unsigned t = gbase[b] + ((unsigned)i - loff[b]);
+                if (t < (unsigned)n) {  // always, for consistent counts
+                    dst[k] = t;
                     part_idx[t] = c;
                 }
             }
