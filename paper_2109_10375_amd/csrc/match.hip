@@ -241,7 +241,15 @@ template <>
 struct Acc<false> {
     unsigned long long v;
     __device__ static Acc zero() { return Acc{0ull}; }
-    __device__ static Acc of(float w, int qmin) { return Acc{scaled_weight(w, qmin).lo}; }
+    // the 64-bit path runs only when the exact total is below 2^64, so every
+    // scaled weight is too (sh < 64 for any weight m > 0)
+    __device__ static Acc of(float w, int qmin) {
+        const unsigned b = __float_as_uint(w);
+        const unsigned e = (b >> 23) & 255u;
+        const unsigned long long m = (b & 0x7fffffu) | (e ? 0x800000u : 0u);
+        const int sh = (e == 0u ? 1 : (int)e) - 150 - qmin;
+        return Acc{((unsigned)sh < 64u) ? m << sh : 0ull};
+    }
     __device__ static Acc of128(u128 x) { return Acc{x.lo}; }
     __device__ Acc operator+(Acc o) const { return Acc{v + o.v}; }
     __device__ Acc shfl_up(int d) const { return Acc{__shfl_up(v, d, 64)}; }
