@@ -47,6 +47,42 @@ def test_halo_radiation_vs_oracle(amber, n, scheme, inter, n_halo):
     assert rel <= 1e-5 and mx <= 2e-5
 
 
+@pytest.mark.parametrize("n", [8, 32])
+def test_empty_catalogue_gives_zero_field(amber, n):
+    plan = amber.Plan(n, 50.0)
+    pos = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+    mass = torch.zeros(0, dtype=torch.float32, device="cuda")
+    Js = plan.radiation_from_halos(pos, mass, [0.5, 3.0])
+    torch.cuda.synchronize()
+    assert all(int(torch.count_nonzero(J)) == 0 for J in Js)
+
+
+@pytest.mark.parametrize("n,scheme,inter", [(32, 1, True), (32, 2, True), (32, 3, True), (8, 3, True),
+                                            (96, 2, False)])
+def test_edge_positions_vs_oracle(amber, n, scheme, inter):
+    """Positions on cell faces and centres, at 0 and just below L, and outside
+    [0, L) (they wrap), against the oracle."""
+    L = 40.0
+    c = L / n
+    below_L = float(np.nextafter(np.float32(L), np.float32(0)))
+    special = np.array([0.0, below_L, c, 2 * c, 0.5 * c, 1.5 * c, L / 2, L - 0.5 * c, -0.25 * c, L + 0.3 * c,
+                        -L + 3.7 * c, 2 * L + 1.1 * c], dtype=np.float32)
+    rng = np.random.default_rng(77 + n + scheme)
+    n_halo = 600
+    pos = special[rng.integers(0, special.size, (n_halo, 3))].astype(np.float32)
+    mass = (10 ** rng.uniform(0, 2, n_halo)).astype(np.float32)
+    plan = amber.Plan(n, L)
+    (J,) = plan.radiation_from_halos(torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda(), [3.0],
+                                     scheme=scheme, interlace=inter)
+    torch.cuda.synchronize()
+    ref = oracle.radiation_from_halos(n, L, pos, mass, scheme, inter, 3.0)
+    Jg = J.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(Jg - ref) / np.linalg.norm(ref)
+    mx = np.max(np.abs(Jg - ref)) / np.max(np.abs(ref))
+    print(f"edge positions n={n} p={scheme}: relL2={rel:.2e} max={mx:.2e}", flush=True)
+    assert rel <= 1e-5 and mx <= 2e-5
+
+
 def test_binned_deposit_is_reproducible(amber):
     """The binned deposit sums exactly: repeated calls give identical fields,
     and so does the catalogue in another order."""
