@@ -106,8 +106,7 @@ WsLayout ws_layout(int n, int n_lmfp, bool halo_meshes) {
     if (halo_meshes) {
         L.mesh[0] = f; f = align256(f + n3 * 4);
         L.mesh[1] = f; f = align256(f + n3 * 4);
-        const size_t tiles = halo_tiles(n);
-        L.bins = f; f = align256(f + (3 * tiles + 4) * 4);
+        L.bins = f; f = align256(f + halo_bin_words(n) * 4);
         L.halo_tab = f; f = align256(f + N * 32);
     }
     // ranking and matching (same region: the stages never overlap on a stream)

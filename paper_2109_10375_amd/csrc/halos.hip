@@ -132,16 +132,57 @@ __device__ __forceinline__ void axis_tiles(double x, int n, bool interlace, int&
     t1 = (int)(wrap(hi + (P - 1), n) / kHaloTile);
 }
 
-// Visits every tile a halo touches (1 to 8), calling f(tile id).
-template <int P, typename F>
-__device__ __forceinline__ void for_each_tile(const double* x, int n, int nt, bool interlace, F f) {
-    int a[3][2];
+// Geometry of the two-level binning: 16^3-cell tiles, nt per axis, grouped
+// into superbins of sb^3 tiles, ns = nt / sb per axis.
+struct Geo {
+    int n, nt, sb, ns;
+    double to_cell;
+    int interlace;
+};
+
+// The tiles a halo touches along each axis (a[d][0], a[d][1], equal when one).
+template <int P>
+__device__ __forceinline__ void halo_axes(float px, float py, float pz, const Geo& g, int (*a)[2]) {
+    const double x[3] = {(double)px * g.to_cell, (double)py * g.to_cell, (double)pz * g.to_cell};
 #pragma unroll
-    for (int d = 0; d < 3; ++d) axis_tiles<P>(x[d], n, interlace, a[d][0], a[d][1]);
-    for (int i = 0; i < (a[0][1] != a[0][0] ? 2 : 1); ++i)
-        for (int j = 0; j < (a[1][1] != a[1][0] ? 2 : 1); ++j)
-            for (int k = 0; k < (a[2][1] != a[2][0] ? 2 : 1); ++k)
-                f((unsigned)((a[0][i] * nt + a[1][j]) * nt + a[2][k]));
+    for (int d = 0; d < 3; ++d) axis_tiles<P>(x[d], g.n, g.interlace != 0, a[d][0], a[d][1]);
+}
+
+// Visits every superbin the halo touches (1 to 8).
+template <typename F>
+__device__ __forceinline__ void for_each_superbin(int (*a)[2], const Geo& g, F f) {
+    int sv[3][2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        sv[d][0] = a[d][0] / g.sb;
+        sv[d][1] = a[d][1] / g.sb;
+    }
+    for (int i = 0; i < (sv[0][1] != sv[0][0] ? 2 : 1); ++i)
+        for (int j = 0; j < (sv[1][1] != sv[1][0] ? 2 : 1); ++j)
+            for (int k = 0; k < (sv[2][1] != sv[2][0] ? 2 : 1); ++k)
+                f((sv[0][i] * g.ns + sv[1][j]) * g.ns + sv[2][k]);
+}
+
+// Visits the touched tiles inside superbin (sx, sy, sz), with the tile's index
+// inside the superbin and its global index.
+template <typename F>
+__device__ __forceinline__ void for_each_tile_in(int (*a)[2], const Geo& g, int sx, int sy, int sz, F f) {
+    const int s3[3] = {sx, sy, sz};
+    int lo[3][2], cnt[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        cnt[d] = 0;
+        const int m = (a[d][1] != a[d][0]) ? 2 : 1;
+        for (int i = 0; i < m; ++i)
+            if (a[d][i] / g.sb == s3[d]) lo[d][cnt[d]++] = a[d][i];
+    }
+    for (int i = 0; i < cnt[0]; ++i)
+        for (int j = 0; j < cnt[1]; ++j)
+            for (int k = 0; k < cnt[2]; ++k) {
+                const int tx = lo[0][i], ty = lo[1][j], tz = lo[2][k];
+                const unsigned local = (unsigned)(((tx - sx * g.sb) * g.sb + (ty - sy * g.sb)) * g.sb + (tz - sz * g.sb));
+                f(local, (unsigned)((tx * g.nt + ty) * g.nt + tz));
+            }
 }
 
 __global__ __launch_bounds__(256) void k_zero_u32(unsigned* __restrict__ p, long long count) {
@@ -149,18 +190,6 @@ __global__ __launch_bounds__(256) void k_zero_u32(unsigned* __restrict__ p, long
          i += (long long)gridDim.x * blockDim.x)
         p[i] = 0u;
 }
-
-// Words of the bins region: the largest |mass| (FP32 bits), the tile counts,
-// the fill cursors, the bin starts (tiles + 1), the gate (1: the bins do not
-// fit), the fixed-point exponent s.
-struct Bins {
-    unsigned* mass_max;
-    unsigned* count;
-    unsigned* cursor;
-    unsigned* start;
-    unsigned* gate;
-    int* sexp;
-};
 
 __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
 #pragma unroll
@@ -171,19 +200,28 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
     return v;
 }
 
+// First level, counts: block b takes halos [b chunk, (b + 1) chunk) and counts
+// per superbin in LDS; cmat[superbin * nb + b] receives the counts (no global
+// atomics), mass_max the largest |mass| bits.
 template <int P>
-__global__ __launch_bounds__(256) void k_bin_count(const float* __restrict__ pos, const float* __restrict__ mass,
-                                                   long long n_halo, int n, int nt, double to_cell, int interlace,
-                                                   unsigned* __restrict__ count, unsigned* __restrict__ mass_max) {
+__global__ __launch_bounds__(256) void k_super_count(const float* __restrict__ pos, const float* __restrict__ mass,
+                                                     long long n_halo, long long chunk, Geo g,
+                                                     unsigned* __restrict__ cmat, int nb,
+                                                     unsigned* __restrict__ mass_max) {
+    __shared__ unsigned h[kHaloSuperMax];
     __shared__ unsigned wmax[4];
+    const int nsup = g.ns * g.ns * g.ns;
+    for (int i = threadIdx.x; i < nsup; i += blockDim.x) h[i] = 0u;
+    __syncthreads();
+    const long long b0 = (long long)blockIdx.x * chunk;
+    const long long b1 = b0 + chunk < n_halo ? b0 + chunk : n_halo;
     unsigned mx = 0u;
-    for (long long h = (long long)blockIdx.x * blockDim.x + threadIdx.x; h < n_halo;
-         h += (long long)gridDim.x * blockDim.x) {
-        const double x[3] = {(double)pos[3 * h] * to_cell, (double)pos[3 * h + 1] * to_cell,
-                             (double)pos[3 * h + 2] * to_cell};
-        const unsigned mb = __float_as_uint(mass[h]) & 0x7fffffffu;
+    for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
+        int a[3][2];
+        halo_axes<P>(pos[3 * e], pos[3 * e + 1], pos[3 * e + 2], g, a);
+        const unsigned mb = __float_as_uint(mass[e]) & 0x7fffffffu;
         mx = mb > mx ? mb : mx;
-        for_each_tile<P>(x, n, nt, interlace != 0, [&](unsigned t) { atomicAdd(&count[t], 1u); });
+        for_each_superbin(a, g, [&](int sbid) { atomicAdd(&h[sbid], 1u); });
     }
     mx = wave_max_u32(mx);
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
@@ -193,11 +231,175 @@ __global__ __launch_bounds__(256) void k_bin_count(const float* __restrict__ pos
         for (int w = 1; w < 4; ++w) m = wmax[w] > m ? wmax[w] : m;
         atomicMax(mass_max, m);
     }
+    for (int i = threadIdx.x; i < nsup; i += blockDim.x) cmat[(long long)i * nb + blockIdx.x] = h[i];
 }
 
-// One block: exclusive prefix of the tile counts into start[] and cursor[],
-// start[tiles] = total, the gate word set when the total exceeds the
-// binned-entry capacity, and the fixed-point exponent s = 62 - E with
+// First level, offsets in two steps.  One block per superbin row of cmat:
+// exclusive prefix of its nb counts into loc[row (nb + 1) + b], the row total
+// in loc[row (nb + 1) + nb] and in rowtot[row].
+__global__ __launch_bounds__(256) void k_row_scan(const unsigned* __restrict__ cmat, int nb,
+                                                  unsigned* __restrict__ loc, unsigned* __restrict__ rowtot) {
+    __shared__ unsigned part[256];
+    const int r = blockIdx.x, t = threadIdx.x;
+    const unsigned* row = cmat + (long long)r * nb;
+    unsigned* out = loc + (long long)r * (nb + 1);
+    const int per = (nb + 255) / 256;
+    const int b = t * per, e = min(nb, b + per);
+    unsigned sum = 0u;
+    for (int i = b; i < e; ++i) sum += row[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const unsigned v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    unsigned run = part[t] - sum;
+    for (int i = b; i < e; ++i) {
+        out[i] = run;
+        run += row[i];
+    }
+    if (t == 0) {
+        out[nb] = part[255];
+        rowtot[r] = part[255];
+    }
+}
+
+// One block: exclusive prefix of the row totals into base[0, nsup], base[nsup]
+// = total; gate_a = 1 when the total exceeds the first level's capacity.
+__global__ __launch_bounds__(1024) void k_rows_scan(const unsigned* __restrict__ rowtot, int nsup,
+                                                    unsigned* __restrict__ base, unsigned long long capacity,
+                                                    unsigned* __restrict__ gate_a) {
+    __shared__ unsigned long long part[1024];
+    const int t = threadIdx.x;
+    const unsigned long long v0 = t < nsup ? rowtot[t] : 0ull;
+    part[t] = v0;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const unsigned long long v = t >= off ? part[t - off] : 0ull;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    const unsigned long long total = part[1023];
+    const bool fits = total <= capacity;
+    if (t < nsup) base[t] = fits ? (unsigned)(part[t] - v0) : 0u;
+    if (t == 0) {
+        base[nsup] = fits ? (unsigned)total : 0u;
+        *gate_a = fits ? 0u : 1u;
+    }
+}
+
+// First level, fill: the same blocks copy (position, mass) into every touched
+// superbin, at offsets reserved by the prefix of cmat (LDS cursors).
+template <int P>
+__global__ __launch_bounds__(256) void k_super_fill(const float* __restrict__ pos, const float* __restrict__ mass,
+                                                    long long n_halo, long long chunk, Geo g,
+                                                    const unsigned* __restrict__ base,
+                                                    const unsigned* __restrict__ loc, int nb,
+                                                    const unsigned* __restrict__ gate_a, float4* __restrict__ ent) {
+    __shared__ unsigned cur[kHaloSuperMax];
+    __shared__ unsigned lim[kHaloSuperMax];
+    if (*gate_a != 0u) return;
+    const int nsup = g.ns * g.ns * g.ns;
+    for (int i = threadIdx.x; i < nsup; i += blockDim.x) {
+        const unsigned* rl = loc + (long long)i * (nb + 1) + blockIdx.x;
+        cur[i] = base[i] + rl[0];
+        lim[i] = base[i] + rl[1];
+    }
+    __syncthreads();
+    const long long b0 = (long long)blockIdx.x * chunk;
+    const long long b1 = b0 + chunk < n_halo ? b0 + chunk : n_halo;
+    for (long long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
+        const float px = pos[3 * e], py = pos[3 * e + 1], pz = pos[3 * e + 2];
+        const float4 v = make_float4(px, py, pz, mass[e]);
+        int a[3][2];
+        halo_axes<P>(px, py, pz, g, a);
+        for_each_superbin(a, g, [&](int sbid) {
+            const unsigned slot = atomicAdd(&cur[sbid], 1u);
+            if (slot < lim[sbid]) ent[slot] = v;  // the counts bound every run
+        });
+    }
+}
+
+// Second level, counts: one block per superbin counts its entries per tile of
+// the superbin (LDS) and writes the tiles' counts (every tile belongs to one
+// superbin, so every count is written).
+template <int P>
+__global__ __launch_bounds__(1024) void k_tile_count(const float4* __restrict__ ent, const unsigned* __restrict__ base,
+                                                     Geo g, const unsigned* __restrict__ gate_a,
+                                                     unsigned* __restrict__ tile_count) {
+    __shared__ unsigned h[kHaloSuperMax];
+    const int sid = blockIdx.x;
+    const int sx = sid / (g.ns * g.ns), sy = (sid / g.ns) % g.ns, sz = sid % g.ns;
+    const int tps = g.sb * g.sb * g.sb;
+    for (int i = threadIdx.x; i < tps; i += blockDim.x) h[i] = 0u;
+    __syncthreads();
+    if (*gate_a == 0u) {
+        const unsigned e0 = base[sid], e1 = base[sid + 1];
+        for (unsigned e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+            const float4 v = ent[e];
+            int a[3][2];
+            halo_axes<P>(v.x, v.y, v.z, g, a);
+            for_each_tile_in(a, g, sx, sy, sz, [&](unsigned local, unsigned) { atomicAdd(&h[local], 1u); });
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < tps; i += blockDim.x) {
+        const int lx = i / (g.sb * g.sb), ly = (i / g.sb) % g.sb, lz = i % g.sb;
+        tile_count[((sx * g.sb + lx) * g.nt + (sy * g.sb + ly)) * g.nt + (sz * g.sb + lz)] = h[i];
+    }
+}
+
+// Second level, fill: the superbin's entries go to their tiles' bins (LDS
+// cursors from the tile starts).
+template <int P>
+__global__ __launch_bounds__(1024) void k_tile_fill(const float4* __restrict__ ent, const unsigned* __restrict__ base,
+                                                    Geo g, const unsigned* __restrict__ gate,
+                                                    const unsigned* __restrict__ start, float4* __restrict__ out) {
+    __shared__ unsigned cur[kHaloSuperMax];
+    if (*gate != 0u) return;
+    const int sid = blockIdx.x;
+    const int sx = sid / (g.ns * g.ns), sy = (sid / g.ns) % g.ns, sz = sid % g.ns;
+    const int tps = g.sb * g.sb * g.sb;
+    for (int i = threadIdx.x; i < tps; i += blockDim.x) {
+        const int lx = i / (g.sb * g.sb), ly = (i / g.sb) % g.sb, lz = i % g.sb;
+        cur[i] = start[((sx * g.sb + lx) * g.nt + (sy * g.sb + ly)) * g.nt + (sz * g.sb + lz)];
+    }
+    __syncthreads();
+    const unsigned e0 = base[sid], e1 = base[sid + 1];
+    for (unsigned e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const float4 v = ent[e];
+        int a[3][2];
+        halo_axes<P>(v.x, v.y, v.z, g, a);
+        for_each_tile_in(a, g, sx, sy, sz, [&](unsigned local, unsigned gid) {
+            const unsigned slot = atomicAdd(&cur[local], 1u);
+            if (slot < start[gid + 1]) out[slot] = v;  // the counts bound every bin
+        });
+    }
+}
+
+// Words of the bins region: the largest |mass| (FP32 bits), the tile counts,
+// the bin starts (tiles + 1), the gate (1: the bins do not fit), the
+// fixed-point exponent s, the first level's gate, count matrix, row
+// prefixes, superbin totals and superbin starts.
+struct Bins {
+    unsigned* mass_max;
+    unsigned* count;
+    unsigned* start;
+    unsigned* gate;
+    int* sexp;
+    unsigned* gate_a;
+    unsigned* cmat;    // counts per (superbin, first-level block)
+    unsigned* loc;     // their prefixes within each superbin row (nb + 1 per row)
+    unsigned* rowtot;  // superbin totals
+    unsigned* base;    // superbin starts (nsup + 1)
+};
+
+// One block: exclusive prefix of the tile counts into start[], start[tiles] =
+// total, the gate word set when the total exceeds the binned-entry capacity or
+// the first level did not fit, and the fixed-point exponent s = 62 - E with
 // |mass| < 2^e and every bin holding at most 2^(E - e) entries, so that every
 // cell's integer sum stays below 2^62 in magnitude (weights are at most 1).
 __global__ __launch_bounds__(1024) void k_bin_scan(Bins bn, int tiles, unsigned long long capacity) {
@@ -227,38 +429,18 @@ __global__ __launch_bounds__(1024) void k_bin_scan(Bins bn, int tiles, unsigned 
     const unsigned long long total = part[1023];
     const bool fits = total <= capacity;
     for (int i = b; i < e; ++i) {
-        const unsigned v = fits ? (unsigned)run : 0u;
-        bn.start[i] = v;
-        bn.cursor[i] = v;
+        bn.start[i] = fits ? (unsigned)run : 0u;
         run += count[i];
     }
     if (t == 0) {
         bn.start[tiles] = fits ? (unsigned)total : 0u;
-        *bn.gate = fits ? 0u : 1u;
+        *bn.gate = (fits && *bn.gate_a == 0u) ? 0u : 1u;
         unsigned c = cmax[0];
         for (int w = 1; w < 16; ++w) c = cmax[w] > c ? cmax[w] : c;
         const unsigned eb = *bn.mass_max >> 23;  // biased exponent of the largest |mass|
         const int e_mass = eb == 0u ? -126 : (int)eb - 126;
         const int e_count = c > 1u ? 32 - __clz(c - 1u) : 0;
         *bn.sexp = 62 - (e_mass + e_count);
-    }
-}
-
-template <int P>
-__global__ __launch_bounds__(256) void k_bin_fill(const float* __restrict__ pos, const float* __restrict__ mass,
-                                                  long long n_halo, int n, int nt, double to_cell, int interlace,
-                                                  unsigned* __restrict__ cursor, const unsigned* __restrict__ start,
-                                                  const unsigned* __restrict__ gate, float4* __restrict__ entries) {
-    if (*gate != 0u) return;
-    for (long long h = (long long)blockIdx.x * blockDim.x + threadIdx.x; h < n_halo;
-         h += (long long)gridDim.x * blockDim.x) {
-        const float px = pos[3 * h], py = pos[3 * h + 1], pz = pos[3 * h + 2];
-        const float4 v = make_float4(px, py, pz, mass[h]);
-        const double x[3] = {(double)px * to_cell, (double)py * to_cell, (double)pz * to_cell};
-        for_each_tile<P>(x, n, nt, interlace != 0, [&](unsigned t) {
-            const unsigned slot = atomicAdd(&cursor[t], 1u);
-            if (slot < start[t + 1]) entries[slot] = v;   // the counts bound every bin
-        });
     }
 }
 
@@ -407,42 +589,59 @@ int halo_source_spectrum(const amber_plan_s* p, const float* d_pos, const float*
     const bool binned = tiles > 0 && n_halo < (1ll << 29);
     const unsigned* gate = nullptr;
     if (binned) {
-        const int nt = n / kHaloTile;
+        Geo g;
+        g.n = n;
+        g.nt = n / kHaloTile;
+        g.sb = (g.nt % 8 == 0) ? 8 : (g.nt % 4 == 0) ? 4 : (g.nt % 2 == 0) ? 2 : 1;
+        g.ns = g.nt / g.sb;
+        g.to_cell = to_cell;
+        g.interlace = interlace;
+        const int nsup = g.ns * g.ns * g.ns;  // <= 512 for N <= 1024
         unsigned* words = reinterpret_cast<unsigned*>(ws + L.bins);
         Bins bn;
         bn.mass_max = words;
         bn.count = words + 1;
-        bn.cursor = bn.count + tiles;
-        bn.start = bn.cursor + tiles;
+        bn.start = bn.count + tiles;
         bn.gate = bn.start + tiles + 1;
         bn.sexp = reinterpret_cast<int*>(bn.gate + 1);
-        unsigned* count = bn.count;
-        unsigned* cursor = bn.cursor;
-        unsigned* start = bn.start;
+        bn.gate_a = bn.gate + 2;
+        bn.cmat = bn.gate + 3;
+        bn.loc = bn.cmat + (size_t)kHaloSuperMax * kHaloSuperBlocks;
+        bn.rowtot = bn.loc + (size_t)kHaloSuperMax * (kHaloSuperBlocks + 1);
+        bn.base = bn.rowtot + kHaloSuperMax;
         gate = bn.gate;
-        float4* entries = reinterpret_cast<float4*>(ws + L.spec_a);
-        const unsigned long long capacity = (L.mesh[0] - L.spec_a) / sizeof(float4);
-        const unsigned hb = (unsigned)std::max<long long>(1, std::min<long long>(16384, (n_halo + 255) / 256));
-        AMBER_LAUNCH(p, "halo_bin_zero", k_zero_u32, dim3((unsigned)((tiles + 256) / 256)), dim3(256), s, words,
-                     (long long)tiles + 1);
+        // first-level copies in the second spectrum, tile bins in the first:
+        // both are written by the forward transforms only after the deposit
+        float4* ent_a = reinterpret_cast<float4*>(ws + L.spec_b);
+        float4* ent_b = reinterpret_cast<float4*>(ws + L.spec_a);
+        const unsigned long long cap_a = (L.mesh[0] - L.spec_b) / sizeof(float4);
+        const unsigned long long cap_b = (L.spec_b - L.spec_a) / sizeof(float4);
+        const int nb = (int)std::max<long long>(1, std::min<long long>(kHaloSuperBlocks, (n_halo + 16383) / 16384));
+        const long long chunk = (n_halo + nb - 1) / nb;
+        AMBER_LAUNCH(p, "halo_bin_zero", k_zero_u32, dim3(1), dim3(256), s, words, 1ll);
+#define AMBER_BINNING(PV)                                                                                          \
+    AMBER_LAUNCH(p, "halo_super_count", k_super_count<PV>, dim3(nb), dim3(256), s, d_pos, d_mass, n_halo, chunk, g,  \
+                 bn.cmat, nb, bn.mass_max);                                                                          \
+    AMBER_LAUNCH(p, "halo_super_scan", k_row_scan, dim3(nsup), dim3(256), s, bn.cmat, nb, bn.loc, bn.rowtot);       \
+    AMBER_LAUNCH(p, "halo_super_scan", k_rows_scan, dim3(1), dim3(1024), s, bn.rowtot, nsup, bn.base, cap_a,        \
+                 bn.gate_a);                                                                                         \
+    AMBER_LAUNCH(p, "halo_super_fill", k_super_fill<PV>, dim3(nb), dim3(256), s, d_pos, d_mass, n_halo, chunk, g,    \
+                 bn.base, bn.loc, nb, bn.gate_a, ent_a);                                                             \
+    AMBER_LAUNCH(p, "halo_tile_count", k_tile_count<PV>, dim3(nsup), dim3(1024), s, ent_a, bn.base, g, bn.gate_a,   \
+                 bn.count);                                                                                          \
+    AMBER_LAUNCH(p, "halo_bin_scan", k_bin_scan, dim3(1), dim3(1024), s, bn, (int)tiles, cap_b);                    \
+    AMBER_LAUNCH(p, "halo_tile_fill", k_tile_fill<PV>, dim3(nsup), dim3(1024), s, ent_a, bn.base, g, gate,          \
+                 bn.start, ent_b);                                                                                   \
+    AMBER_LAUNCH(p, "halo_deposit", k_tile_deposit<PV>, dim3((unsigned)tiles), dim3(256), s, ent_b, bn.start, gate, \
+                 bn.sexp, n, g.nt, to_cell, mesh0, m1);
         if (scheme == 1) {
-            AMBER_LAUNCH(p, "halo_bin_count", k_bin_count<1>, dim3(hb), dim3(256), s, d_pos, d_mass, n_halo, n, nt, to_cell, interlace, count, bn.mass_max);
+            AMBER_BINNING(1)
         } else if (scheme == 2) {
-            AMBER_LAUNCH(p, "halo_bin_count", k_bin_count<2>, dim3(hb), dim3(256), s, d_pos, d_mass, n_halo, n, nt, to_cell, interlace, count, bn.mass_max);
+            AMBER_BINNING(2)
         } else {
-            AMBER_LAUNCH(p, "halo_bin_count", k_bin_count<3>, dim3(hb), dim3(256), s, d_pos, d_mass, n_halo, n, nt, to_cell, interlace, count, bn.mass_max);
+            AMBER_BINNING(3)
         }
-        AMBER_LAUNCH(p, "halo_bin_scan", k_bin_scan, dim3(1), dim3(1024), s, bn, (int)tiles, capacity);
-        if (scheme == 1) {
-            AMBER_LAUNCH(p, "halo_bin_fill", k_bin_fill<1>, dim3(hb), dim3(256), s, d_pos, d_mass, n_halo, n, nt, to_cell, interlace, cursor, start, gate, entries);
-            AMBER_LAUNCH(p, "halo_deposit", k_tile_deposit<1>, dim3((unsigned)tiles), dim3(256), s, entries, start, gate, bn.sexp, n, nt, to_cell, mesh0, m1);
-        } else if (scheme == 2) {
-            AMBER_LAUNCH(p, "halo_bin_fill", k_bin_fill<2>, dim3(hb), dim3(256), s, d_pos, d_mass, n_halo, n, nt, to_cell, interlace, cursor, start, gate, entries);
-            AMBER_LAUNCH(p, "halo_deposit", k_tile_deposit<2>, dim3((unsigned)tiles), dim3(256), s, entries, start, gate, bn.sexp, n, nt, to_cell, mesh0, m1);
-        } else {
-            AMBER_LAUNCH(p, "halo_bin_fill", k_bin_fill<3>, dim3(hb), dim3(256), s, d_pos, d_mass, n_halo, n, nt, to_cell, interlace, cursor, start, gate, entries);
-            AMBER_LAUNCH(p, "halo_deposit", k_tile_deposit<3>, dim3((unsigned)tiles), dim3(256), s, entries, start, gate, bn.sexp, n, nt, to_cell, mesh0, m1);
-        }
+#undef AMBER_BINNING
     } else {
         const unsigned zero_blocks = (unsigned)std::min<long long>(4096, (n3 + 255) / 256);
         AMBER_LAUNCH(p, "halo_zero", k_zero_f32, dim3(zero_blocks), dim3(256), s, mesh0, n3);

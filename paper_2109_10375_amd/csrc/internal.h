@@ -147,6 +147,13 @@ inline size_t halo_tiles(int n) {
     const size_t t = (n % kHaloTile == 0) ? (size_t)(n / kHaloTile) : 0;
     return t * t * t;
 }
+// The binning's first level: up to this many superbins of up to this many
+// tiles each, and up to this many blocks (one count per superbin and block).
+constexpr int kHaloSuperMax = 512;
+constexpr int kHaloSuperBlocks = 2048;
+inline size_t halo_bin_words(int n) {
+    return 2 * halo_tiles(n) + 8 + (size_t)kHaloSuperMax * (2 * kHaloSuperBlocks + 1) + 2 * kHaloSuperMax + 1;
+}
 
 // Halo catalogue -> interlaced, deconvolved source spectrum in spec_a (halos.hip).
 int halo_source_spectrum(const amber_plan_s* p, const float* d_pos, const float* d_mass, long long n_halo,
