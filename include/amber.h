@@ -157,11 +157,12 @@ size_t amber_halo_workspace_bytes(amber_plan plan);
  *   J_l = Re IDFT[S(k) Khat(|k|; l)] / N^3 for each l_mfp, as amber_radiation.
  * d_pos: device, n_halo x 3 FP32 positions in [0, box_len) (others wrap);
  * d_mass: device, n_halo finite FP32 masses.  When 16 divides N and the
- * binned copies of the catalogue fit in the workspace's spectrum region (up
- * to (8 N^3 + 16 N^2) / 16 halo-tile pairs, about 1.4 per halo for CIC with
- * interlacing), each mesh cell is the exact sum of its terms rounded once to
- * FP32 and J is identical from call to call; otherwise the deposit falls back
- * to FP32 global atomics, whose last bits depend on their order. */
+ * binned copies of the catalogue fit in the workspace's two spectrum regions
+ * (up to (4 N^3 + 8 N^2) / 16 halo-superbin pairs, about 1.05 per halo, and as
+ * many halo-tile pairs, about 1.4 per halo for CIC with interlacing), each
+ * mesh cell is the exact sum of its terms rounded once to FP32 and J is
+ * identical from call to call; otherwise the deposit falls back to FP32
+ * global atomics, whose last bits depend on their order. */
 int amber_radiation_from_halos(amber_plan plan, const float* d_pos, const float* d_mass, int64_t n_halo,
                                int scheme, int interlace, const double* l_mfp, int n_lmfp, float* const* d_J,
                                void* d_ws, size_t ws_bytes, void* stream);
