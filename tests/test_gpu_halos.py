@@ -26,11 +26,14 @@ def amber():
     return amber
 
 
-# (8, ...) has no 16^3 tiles and (16, ..., 6000) more binned copies than the
-# workspace holds: both take the direct atomic deposit
+# (8, ...) has no 16^3 tiles, (16, ..., 6000) more superbin copies than the
+# workspace holds and (32, ..., 7500) fits its superbin copies (~7500) but not
+# its tile copies (~1.4 per halo, room for 8704): all three take the direct
+# atomic deposit
 @pytest.mark.parametrize("n,scheme,inter,n_halo", [(16, 1, False, 0), (32, 2, False, 0), (32, 2, True, 0),
                                                    (64, 3, True, 0), (96, 2, True, 0), (64, 1, True, 0),
-                                                   (8, 2, True, 300), (16, 3, True, 6000), (192, 2, True, 0)])
+                                                   (8, 2, True, 300), (16, 3, True, 6000), (32, 2, True, 7500),
+                                                   (192, 2, True, 0)])
 def test_halo_radiation_vs_oracle(amber, n, scheme, inter, n_halo):
     n_halo = n_halo or max(2000, n ** 3 // 20)
     cfg = inputs.BoxConfig("hal", n, 1.5625 * n, n_halo, 1e9, 1e12, index=800 + n)
