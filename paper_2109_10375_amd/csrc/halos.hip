@@ -14,18 +14,21 @@
 //
 // Deposit: on grids that 16 divides, halos are binned by 16^3 mesh tile (a
 // halo joins the bin of every tile its window touches on either mesh: one to
-// eight), then one workgroup per tile sums its bin into the tile's cells in
-// LDS and writes the block with plain stores, so the meshes need neither
-// zeroing nor global atomics.  The LDS sums are exact: every term m w_x w_y w_z
+// eight) in two levels: blocks of the catalogue count and copy their halos
+// per superbin of up to 8^3 tiles with LDS counters (offsets from a scan of
+// the per-block counts), then one workgroup per superbin counts and copies its
+// halos into its tiles' bins.  One workgroup per tile then sums its bin into
+// the tile's cells in LDS and writes the block with plain stores, so the
+// meshes need neither zeroing nor global atomics.  The LDS sums are exact: every term m w_x w_y w_z
 // (FP64 from the FP32 position and mass) is rounded once to a 64-bit integer
 // multiple of 2^-s, s chosen from the largest |mass| and the largest bin so
 // that no cell sum can overflow, and added with integer atomics; each cell is
 // then rounded once to FP32.  The mesh therefore does not depend on the order
 // of the halos or of the atomics, and repeated calls give identical fields.
-// The binned copies live in the spectrum region, which the forward transforms
-// only write afterwards; when they would not fit there (or on other grids)
-// every halo adds its FP32 terms with global atomics instead, whose last bits
-// depend on the order of the additions.
+// The superbin copies and the tile bins live in the two spectrum regions,
+// which the forward transforms only write afterwards; when they would not fit
+// there (or on other grids) every halo adds its FP32 terms with global atomics
+// instead, whose last bits depend on the order of the additions.
 #include <algorithm>
 
 #include "internal.h"
