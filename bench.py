@@ -44,7 +44,7 @@ WORKLOADS = {
                                   "of the 1024^3 box, 513 shells: two forward FFTs and the shell reduction"),
     "c5": dict(cfg=None, desc="Poisson requests at 20/s for 60 s, N in {128,256,512,1024} w.p. 0.4/0.3/0.2/0.1, "
                              "l_mfp and history from the 512^3 sweep sets; resident boxes, HBM-budget admission, "
-                             "same-N batching"),
+                             "same-N batches admitted into free stream slots while others run (continuous batching)"),
 }
 
 
@@ -389,7 +389,7 @@ def bench_serving(args) -> dict:
         log(f"[bench] generating the resident {n}^3 box")
         w, S = inputs.make_box(cfg, device=dev, dtype=torch.float32)
         boxes[n] = serve.Box(amber.Plan(n, cfg.box_len), S, w)
-    server = serve.Server(boxes, hbm_budget_bytes=args.hbm_budget_gb * 2 ** 30, max_batch=16)
+    server = serve.Server(boxes, hbm_budget_bytes=args.hbm_budget_gb * 2 ** 30, max_batch=16, slots=args.serve_slots)
     warm = serve.requests_from(inputs.c5_requests(2.0, seed=55))
     server.serve(warm)
     reqs = serve.requests_from(inputs.c5_requests(args.serve_seconds))
@@ -402,6 +402,7 @@ def bench_serving(args) -> dict:
                     "mean_latency_ms": round(st["mean_ms"], 3), "requests": st["requests"],
                     "batches": st["batches"], "offered_cells_per_s": offered,
                     "makespan_s": round(st["makespan_s"], 3), "busy_s": round(st["busy_s"], 3),
+                    "slots": st["slots"], "max_batches_in_flight": st["max_batches_in_flight"],
                     "hbm_budget_gb": args.hbm_budget_gb, "arrivals_s": args.serve_seconds})
 
 
@@ -416,6 +417,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="c5: seconds of Poisson arrivals")
     ap.add_argument("--hbm-budget-gb", type=int, default=96, help="c5: HBM for outputs of requests in flight")
+    ap.add_argument("--serve-slots", type=int, default=2, help="c5: streams with batches in flight at once")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain copy of MIB MiB (for HBM counter calibration)")
     args = ap.parse_args()

@@ -128,3 +128,10 @@ def test_growth_table_identical_to_oracle(hist, z_mid):
     g_or = oracle.growth_table(H, z_mid)
     assert g_lib.shape == g_or.shape
     assert np.array_equal(g_lib.view(np.uint64), g_or.view(np.uint64))
+
+
+def test_serving_busy_time_is_the_union_of_batch_intervals():
+    from paper_2109_10375_amd.serve import _union
+    assert _union([]) == 0.0
+    assert _union([(0.0, 1.0), (0.5, 2.0), (3.0, 4.0)]) == pytest.approx(3.0)
+    assert _union([(1.0, 2.0), (0.0, 5.0)]) == pytest.approx(5.0)
