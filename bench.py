@@ -195,6 +195,29 @@ def _common(args, metric: str, value: float, ms: float, desc: str, extra: dict) 
     return out
 
 
+def tune_fft(plan, S, args, known: dict | None = None) -> dict:
+    """Sets the plan's FFT launch schedule: timed by the library's tuner on S
+    (or read from --tune-cache), or the default pair with --no-tune.  `known`
+    maps a grid size to a pair already chosen for another plan of that size."""
+    import paper_2109_10375_amd as amber
+
+    cand = amber.fft_schedules(plan.n)
+    if args.no_tune:
+        return {"col": list(cand["col"][0]), "z": list(cand["z"][0]), "tuned": False}
+    if known is not None and plan.n in known:
+        plan.set_schedule(*known[plan.n])
+        c, z = known[plan.n]
+        return {"col": list(cand["col"][c]), "z": list(cand["z"][z]), "tuned": True, "cached": True}
+    t = time.perf_counter()
+    res = amber.tune_plan(plan, S, reps=args.tune_reps, cache=args.tune_cache)
+    if known is not None:
+        known[plan.n] = (res["col"], res["z"])
+    log(f"[bench] FFT schedule n={plan.n}: column (N1, C) = {tuple(res['col_split'])}, z (M1, ZL) = "
+        f"{tuple(res['z_split'])}{' from the cache' if res['cached'] else ''} ({time.perf_counter() - t:.1f} s); "
+        f"ms per radiation pass by [column][z] candidate: {[[round(x, 3) for x in row] for row in res['ms']]}")
+    return {"col": res["col_split"], "z": res["z_split"], "tuned": True, "cached": res["cached"]}
+
+
 def _time_steps(fn, steps: int, warmup: int):
     import torch
 
@@ -234,6 +257,7 @@ def bench_sweep(args) -> dict:
     w, S = inputs.make_box(cfg, device=dev, dtype=torch.float32)
     n, ls = cfg.n, list(cfg.l_mfp)
     plan = amber.Plan(n, cfg.box_len)
+    sched = tune_fft(plan, S, args)
     hists = [amber.History.from_params(*h) for h in cfg.histories]
     J = [torch.empty((n, n, n), dtype=torch.float32, device=dev) for _ in ls]
     Z = [[torch.empty((n, n, n), dtype=torch.float32, device=dev) for _ in hists] for _ in ls]
@@ -254,7 +278,7 @@ def bench_sweep(args) -> dict:
                    {"p50_ms": round(_pct(ms, 50), 3), "p99_ms": round(_pct(ms, 99), 3),
                     "serial_single_calls": {"value": fields / el_s, "ms_per_step": 1e3 * el_s / args.steps,
                                             "p50_ms": round(_pct(ms_s, 50), 3)},
-                    "zre_fields_per_step": len(ls) * len(hists)})
+                    "zre_fields_per_step": len(ls) * len(hists), "fft_schedule": sched})
 
 
 def bench_mixed(args) -> dict:
@@ -268,11 +292,13 @@ def bench_mixed(args) -> dict:
     dev = torch.device("cuda", 0)
     cfgs = inputs.c4_boxes(64)
     items, singles = [], []
+    known, scheds = {}, {}
     log(f"[bench] generating {len(cfgs)} boxes")
     for cfg in cfgs:
         w, S = inputs.make_box(cfg, device=dev, dtype=torch.float32)
         n = cfg.n
         plan = amber.Plan(n, cfg.box_len)
+        scheds[str(n)] = tune_fft(plan, S, args, known)
         h = amber.History.from_params(*cfg.histories[0])
         J = torch.empty((n, n, n), dtype=torch.float32, device=dev)
         z = torch.empty_like(J)
@@ -305,7 +331,8 @@ def bench_mixed(args) -> dict:
                     "p50_ms": round(_pct(ms_g, 50), 3), "p99_ms": round(_pct(ms_g, 99), 3),
                     "eager_batch": {"value": args.steps * cells / el_e, "ms_per_step": 1e3 * el_e / args.steps},
                     "serial_single_calls": {"value": args.steps * cells / el_s,
-                                            "ms_per_step": 1e3 * el_s / args.steps}})
+                                            "ms_per_step": 1e3 * el_s / args.steps},
+                    "fft_schedule": scheds})
 
 
 def bench_spectra(args) -> dict:
@@ -319,6 +346,7 @@ def bench_spectra(args) -> dict:
     dev = torch.device("cuda", 0)
     w, S = inputs.make_box(cfg, device=dev, dtype=torch.float32)
     plan = amber.Plan(cfg.n, cfg.box_len)
+    sched = tune_fft(plan, S, args)
     hist = amber.History.from_params(*cfg.histories[0])
     (J,) = plan.radiation(S, [cfg.l_mfp[0]])
     (z,) = plan.zre(J, w, [hist])
@@ -336,7 +364,8 @@ def bench_spectra(args) -> dict:
                    1e3 * el / args.steps, WORKLOADS["spectra"]["desc"],
                    {"p50_ms": round(_pct(ms, 50), 3), "p99_ms": round(_pct(ms, 99), 3),
                     "r_zd_at_k": {f"{float(r['k'][i]):.4f}": round(float(r["r"][i]), 4) for i in (1, 4, 16, 64, 256)},
-                    "b_zd_at_k": {f"{float(r['k'][i]):.4f}": round(float(r["bias"][i]), 4) for i in (1, 4, 16, 64, 256)}})
+                    "b_zd_at_k": {f"{float(r['k'][i]):.4f}": round(float(r["bias"][i]), 4) for i in (1, 4, 16, 64, 256)},
+                    "fft_schedule": sched})
 
 
 def bench_halos(args) -> dict:
@@ -352,6 +381,7 @@ def bench_halos(args) -> dict:
     w = inputs.make_density(n, inputs.config_seed(cfg.index, 0), device=dev, dtype=torch.float32).to(torch.float32)
     pos, mass = inputs.make_halos(cfg, device=dev, w=w)
     plan = amber.Plan(n, cfg.box_len)
+    sched = tune_fft(plan, w, args)   # any N^3 field times the same passes
     hist = amber.History.from_params(*cfg.histories[0])
     J = torch.empty((n, n, n), dtype=torch.float32, device=dev)
     z = torch.empty_like(J)
@@ -370,7 +400,8 @@ def bench_halos(args) -> dict:
                    args.steps * n ** 3 / el, 1e3 * el / args.steps, WORKLOADS["H_halos"]["desc"],
                    {"p50_ms": round(_pct(ms, 50), 3), "p99_ms": round(_pct(ms, 99), 3), "n_halo": cfg.n_halo,
                     "kernels_ms_per_step": {k: round(t / args.steps, 4)
-                                            for k, (c, t) in sorted(prof.items(), key=lambda kv: -kv[1][1])}})
+                                            for k, (c, t) in sorted(prof.items(), key=lambda kv: -kv[1][1])},
+                    "fft_schedule": sched})
 
 
 def bench_serving(args) -> dict:
@@ -382,13 +413,14 @@ def bench_serving(args) -> dict:
     from paper_2109_10375_amd import serve
 
     dev = torch.device("cuda", 0)
-    boxes = {}
+    boxes, scheds = {}, {}
     for n in (128, 256, 512, 1024):
         cfg = inputs.BoxConfig(f"c5.{n}", n, 1.953125 * n, max(1000, int(1.3e6 * (n / 256) ** 3)), 1e10, 1e12,
                                index=200 + n)
         log(f"[bench] generating the resident {n}^3 box")
         w, S = inputs.make_box(cfg, device=dev, dtype=torch.float32)
         boxes[n] = serve.Box(amber.Plan(n, cfg.box_len), S, w)
+        scheds[str(n)] = tune_fft(boxes[n].plan, S, args)
     server = serve.Server(boxes, hbm_budget_bytes=args.hbm_budget_gb * 2 ** 30, max_batch=16, slots=args.serve_slots)
     warm = serve.requests_from(inputs.c5_requests(2.0, seed=55))
     server.serve(warm)
@@ -403,7 +435,8 @@ def bench_serving(args) -> dict:
                     "batches": st["batches"], "offered_cells_per_s": offered,
                     "makespan_s": round(st["makespan_s"], 3), "busy_s": round(st["busy_s"], 3),
                     "slots": st["slots"], "max_batches_in_flight": st["max_batches_in_flight"],
-                    "hbm_budget_gb": args.hbm_budget_gb, "arrivals_s": args.serve_seconds})
+                    "hbm_budget_gb": args.hbm_budget_gb, "arrivals_s": args.serve_seconds,
+                    "fft_schedule": scheds})
 
 
 def main() -> int:
@@ -418,6 +451,10 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="c5: seconds of Poisson arrivals")
     ap.add_argument("--hbm-budget-gb", type=int, default=96, help="c5: HBM for outputs of requests in flight")
     ap.add_argument("--serve-slots", type=int, default=2, help="c5: streams with batches in flight at once")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default FFT schedule (no autotuning)")
+    ap.add_argument("--tune-reps", type=int, default=5, help="timed radiation passes per schedule pair and round")
+    ap.add_argument("--tune-cache", default=None, metavar="JSON",
+                    help="schedule cache keyed by device and grid size (default: tune in this process)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain copy of MIB MiB (for HBM counter calibration)")
     args = ap.parse_args()
@@ -452,6 +489,7 @@ def main() -> int:
     log(f"[bench] inputs ready in {time.perf_counter() - tg:.1f} s")
 
     plan = amber.Plan(n, cfg.box_len)
+    sched = tune_fft(plan, S, args)
     hist = amber.History.from_params(*cfg.histories[0])
     if wl.get("growth"):
         hist = hist.with_growth(cfg.histories[0][0])
@@ -530,7 +568,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n": n, "box_len": cfg.box_len, "n_halo": cfg.n_halo,
                    "l_mfp": l_mfp[0], "history": list(cfg.histories[0]),
-                   "precision": "FFT f32; mass prefix exact int128; F and inversion f64"},
+                   "precision": "FFT f32; mass prefix exact int128; F and inversion f64",
+                   "fft_schedule": sched},
         "p50_ms": round(pct(50), 3),
         "p99_ms": round(pct(99), 3),
         "pipeline_alg_bytes_per_step": pipe_bytes,

@@ -139,6 +139,44 @@ size_t amber_workspace_bytes(amber_plan plan, int n_lmfp);
 int amber_radiation(amber_plan plan, const float* d_src, const double* l_mfp, int n_lmfp,
                     float* const* d_J, void* d_ws, size_t ws_bytes, void* stream);
 
+/* ---- FFT launch schedules and the tuner ---------------------------------- */
+
+/* The FFTs inside amber_radiation, amber_radiation_from_halos and
+ * amber_spectra (the DFTs of Sec. 3.4.1 and Sec. 3.2.1) run as column passes,
+ * which split a length-N transform into N1 x (N/N1) over N1 threads and take
+ * tiles of C columns, and z passes, which split the length-N/2 complex
+ * transform of the real lines into M1 x (N/2/M1) over M1 threads and take ZL
+ * lines per block.  Several (N1, C) and (M1, ZL) candidates are compiled per
+ * grid size; candidate 0 is the default.  All candidates compute the same
+ * transforms; they differ in FP32 rounding order only.
+ *
+ * Number of column-pass and z-pass candidates for grid size n (host only, no
+ * device call).  AMBER_E_SIZE for an unsupported n. */
+int amber_fft_schedules(int n, int* n_col, int* n_z);
+
+/* Split of candidate idx: kind 0 gives (N1, C) of a column pass, kind 1
+ * (M1, ZL) of a z pass.  Host only.  AMBER_E_ARG for a bad kind or idx. */
+int amber_fft_schedule_info(int n, int kind, int idx, int* split, int* width);
+
+/* Chooses the candidates later calls on this plan use (not thread-safe with
+ * calls in flight on other host threads).  AMBER_E_ARG when out of range. */
+int amber_plan_set_schedule(amber_plan plan, int col, int z);
+int amber_plan_get_schedule(amber_plan plan, int* col, int* z);
+
+/* Autotuner: times one radiation pass (one mean free path) of d_src into d_J
+ * under every (column, z) candidate pair, `reps` passes per pair after one
+ * untimed pass, in three rounds (a pair's figure is its fastest round), and
+ * sets the plan to the fastest pair.  The default pair is kept unless another
+ * is faster by more than 2 %.  d_src: N^3 FP32 (read only); d_J: N^3 FP32
+ * scratch, overwritten; d_ws: amber_workspace_bytes(plan, 1) bytes.
+ * ms_out: host array of n_col * n_z floats (row-major [col][z], mean ms per
+ * pass), may be NULL; col, z: the chosen pair, may be NULL.  Creates and
+ * destroys two HIP events and blocks the host until the timing passes end;
+ * launches are not traced by amber_profile_begin.  On error the plan keeps
+ * the schedule it had. */
+int amber_plan_tune(amber_plan plan, const float* d_src, float* d_J, void* d_ws, size_t ws_bytes, int reps,
+                    float* ms_out, int* col, int* z, void* stream);
+
 /* Mass-assignment windows for halo sources (Sec. 3.2.1, Eq. Wofk: p = 1, 2, 3). */
 #define AMBER_ASSIGN_NGP 1
 #define AMBER_ASSIGN_CIC 2
@@ -272,9 +310,9 @@ typedef struct {
 } amber_kernel_time;
 
 /* Starts timing the kernels that later compute calls on this plan launch:
- * creates `capacity` pairs of HIP events (the only time the library creates
- * events); launches beyond capacity are not timed.  Calls on several streams
- * are timed each on its own stream. */
+ * creates `capacity` pairs of HIP events (besides the tuner's two, the only
+ * events the library creates); launches beyond capacity are not timed.  Calls
+ * on several streams are timed each on its own stream. */
 int amber_profile_begin(amber_plan plan, int capacity);
 
 /* Waits for the recorded events, writes up to max_entries per-kernel totals

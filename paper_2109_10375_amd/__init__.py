@@ -15,9 +15,11 @@ from ._lib import (  # noqa: F401
     STATUS_BAD_W,
     STATUS_NAN_J,
     STATUS_RANGE,
+    fft_schedules,
     lib,
     library_path,
 )
+from .tune import tune_plan  # noqa: F401
 
-__all__ = ["AmberError", "Batch", "BatchItem", "History", "Plan", "lib", "library_path",
+__all__ = ["AmberError", "Batch", "BatchItem", "History", "Plan", "fft_schedules", "lib", "library_path", "tune_plan",
            "STATUS_NAN_J", "STATUS_BAD_W", "STATUS_RANGE"]

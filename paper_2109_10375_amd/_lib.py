@@ -25,6 +25,8 @@ SYMBOLS = [
     "amber_radiation", "amber_rank", "amber_zre", "amber_status", "amber_profile_begin",
     "amber_profile_end", "amber_batch_workspace_bytes", "amber_batch_run", "amber_spectra_workspace_bytes",
     "amber_spectra", "amber_growth_table", "amber_halo_workspace_bytes", "amber_radiation_from_halos",
+    "amber_fft_schedules", "amber_fft_schedule_info", "amber_plan_set_schedule", "amber_plan_get_schedule",
+    "amber_plan_tune",
 ]
 ASSIGN_NGP, ASSIGN_CIC, ASSIGN_TSC = 1, 2, 3
 FIELD_RAW, FIELD_OVERDENSITY, FIELD_REDSHIFT = 0, 1, 2
@@ -103,6 +105,12 @@ def lib() -> ctypes.CDLL:
         L.amber_spectra_workspace_bytes.argtypes = [vp]
         L.amber_spectra_workspace_bytes.restype = sz
         L.amber_spectra.argtypes = [vp, vp, i, vp, i, i, vp, vp, sz, vp]
+        ip = ctypes.POINTER(i)
+        L.amber_fft_schedules.argtypes = [i, ip, ip]
+        L.amber_fft_schedule_info.argtypes = [i, i, i, ip, ip]
+        L.amber_plan_set_schedule.argtypes = [vp, i, i]
+        L.amber_plan_get_schedule.argtypes = [vp, ip, ip]
+        L.amber_plan_tune.argtypes = [vp, vp, vp, vp, sz, i, ctypes.POINTER(ctypes.c_float), ip, ip, vp]
         _lib = L
     return _lib
 
@@ -180,6 +188,22 @@ class History:
         _check(lib().amber_growth_table(ctypes.byref(w), float(z_mid), float(omega_m),
                                         ctypes.c_void_p(host.data_ptr()), w.table_n), "amber_growth_table")
         return host
+
+
+def fft_schedules(n: int) -> dict:
+    """amber_fft_schedules + amber_fft_schedule_info: the compiled FFT launch
+    candidates for grid size n, {"col": [(N1, C), ...], "z": [(M1, ZL), ...]}
+    (index 0 is the default).  Host only."""
+    nc, nz = ctypes.c_int(), ctypes.c_int()
+    _check(lib().amber_fft_schedules(int(n), ctypes.byref(nc), ctypes.byref(nz)), "amber_fft_schedules")
+    out = {"col": [], "z": []}
+    for kind, key, count in ((0, "col", nc.value), (1, "z", nz.value)):
+        for idx in range(count):
+            a, b = ctypes.c_int(), ctypes.c_int()
+            _check(lib().amber_fft_schedule_info(int(n), kind, idx, ctypes.byref(a), ctypes.byref(b)),
+                   "amber_fft_schedule_info")
+            out[key].append((a.value, b.value))
+    return out
 
 
 class Plan:
@@ -288,6 +312,32 @@ class Plan:
         rows = out.view(8, nb).cpu()
         names = ("k", "modes", "p_aa", "p_bb", "p_ab", "delta2_aa", "bias", "r")
         return {name: rows[i] for i, name in enumerate(names)}
+
+    @property
+    def schedule(self) -> tuple:
+        """amber_plan_get_schedule: (column candidate, z candidate)."""
+        c, z = ctypes.c_int(), ctypes.c_int()
+        _check(lib().amber_plan_get_schedule(self._h, ctypes.byref(c), ctypes.byref(z)), "amber_plan_get_schedule")
+        return (c.value, z.value)
+
+    def set_schedule(self, col: int, z: int) -> None:
+        """amber_plan_set_schedule."""
+        _check(lib().amber_plan_set_schedule(self._h, int(col), int(z)), "amber_plan_set_schedule")
+
+    def tune(self, S: torch.Tensor, reps: int = 5) -> dict:
+        """amber_plan_tune: time every FFT candidate pair on S and keep the
+        fastest.  Returns {"col", "z", "ms": [[ms per pass] per z] per col}."""
+        cand = fft_schedules(self.n)
+        nc, nz = len(cand["col"]), len(cand["z"])
+        J = torch.empty((self.n,) * 3, dtype=torch.float32, device=self.device)
+        ms = (ctypes.c_float * (nc * nz))()
+        c, z = ctypes.c_int(), ctypes.c_int()
+        ws = self.workspace(1)
+        _check(lib().amber_plan_tune(self._h, _dev_ptr(S, torch.float32, self.n3, "S"),
+                                     _dev_ptr(J, torch.float32, self.n3, "J"), ctypes.c_void_p(ws.data_ptr()),
+                                     ws.numel(), int(reps), ms, ctypes.byref(c), ctypes.byref(z), _stream()),
+               "amber_plan_tune")
+        return {"col": c.value, "z": z.value, "ms": [[float(ms[a * nz + b]) for b in range(nz)] for a in range(nc)]}
 
     def profile_begin(self, capacity: int = 4096) -> None:
         """amber_profile_begin: time every kernel of the following calls."""

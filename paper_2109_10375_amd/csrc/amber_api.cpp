@@ -346,6 +346,110 @@ int amber_radiation(amber_plan plan, const float* d_src, const double* l_mfp, in
                          static_cast<hipStream_t>(stream));
 }
 
+int amber_fft_schedules(int n, int* n_col, int* n_z) {
+    if (!n_col || !n_z) return AMBER_E_ARG;
+    return fft_schedule_count(n, n_col, n_z);
+}
+
+int amber_fft_schedule_info(int n, int kind, int idx, int* split, int* width) {
+    if (!split || !width || idx < 0) return AMBER_E_ARG;
+    return fft_schedule_info(n, kind, idx, split, width);
+}
+
+int amber_plan_set_schedule(amber_plan plan, int col, int z) {
+    if (!plan) return AMBER_E_ARG;
+    int nc = 0, nz = 0;
+    const int rc = fft_schedule_count(plan->n, &nc, &nz);
+    if (rc != AMBER_OK) return rc;
+    if (col < 0 || col >= nc || z < 0 || z >= nz) return AMBER_E_ARG;
+    plan->col_sched = col;
+    plan->z_sched = z;
+    return AMBER_OK;
+}
+
+int amber_plan_get_schedule(amber_plan plan, int* col, int* z) {
+    if (!plan || !col || !z) return AMBER_E_ARG;
+    *col = plan->col_sched;
+    *z = plan->z_sched;
+    return AMBER_OK;
+}
+
+namespace {
+
+// Mean time of one radiation pass (one l_mfp) under the plan's current
+// schedule: one untimed pass, then reps passes between two events.
+int time_radiation(amber_plan_s* p, const float* d_src, float* d_J, unsigned char* ws, const WsLayout& L, int reps,
+                   hipEvent_t e0, hipEvent_t e1, hipStream_t s, float* ms) {
+    const double l = p->box_len / 16.0;
+    float* out[1] = {d_J};
+    int rc = fft_radiation(p, d_src, &l, 1, out, ws, L, s);
+    if (rc != AMBER_OK) return rc;
+    AMBER_HIP_CHECK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) {
+        rc = fft_radiation(p, d_src, &l, 1, out, ws, L, s);
+        if (rc != AMBER_OK) return rc;
+    }
+    AMBER_HIP_CHECK(hipEventRecord(e1, s));
+    AMBER_HIP_CHECK(hipEventSynchronize(e1));
+    float t = 0.f;
+    AMBER_HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
+    *ms = t / (float)reps;
+    return AMBER_OK;
+}
+
+}  // namespace
+
+int amber_plan_tune(amber_plan plan, const float* d_src, float* d_J, void* d_ws, size_t ws_bytes, int reps,
+                    float* ms_out, int* col, int* z, void* stream) {
+    if (!plan || !d_src || !d_J || !d_ws || (const void*)d_J == (const void*)d_src) return AMBER_E_ARG;
+    if (reps < 1 || reps > 1000) return AMBER_E_ARG;
+    const WsLayout L = ws_layout(plan->n, 1);
+    if (ws_bytes < L.total) return AMBER_E_WORKSPACE;
+    int nc = 0, nz = 0;
+    int rc = fft_schedule_count(plan->n, &nc, &nz);
+    if (rc != AMBER_OK) return rc;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned char* ws = static_cast<unsigned char*>(d_ws);
+    const int keep_col = plan->col_sched, keep_z = plan->z_sched;
+    Profiler* keep_prof = plan->prof;  // tuning launches are not traced
+    plan->prof = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float best_ms[64 * 64];
+    const int n_all = nc * nz;
+    if (n_all > 64 * 64) rc = AMBER_E_ARG;
+    if (rc == AMBER_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = AMBER_E_HIP;
+    // Three rounds over every candidate pair; a pair's figure is its fastest
+    // round, which discounts clock ramps and one-off stalls.
+    for (int round = 0; rc == AMBER_OK && round < 3; ++round) {
+        for (int k = 0; rc == AMBER_OK && k < n_all; ++k) {
+            plan->col_sched = k / nz;
+            plan->z_sched = k % nz;
+            float ms = 0.f;
+            rc = time_radiation(plan, d_src, d_J, ws, L, reps, e0, e1, s, &ms);
+            if (rc == AMBER_OK) best_ms[k] = (round == 0) ? ms : std::min(best_ms[k], ms);
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    plan->prof = keep_prof;
+    if (rc != AMBER_OK) {
+        plan->col_sched = keep_col;
+        plan->z_sched = keep_z;
+        return rc;
+    }
+    // The default pair stays unless another is faster by more than 2 %: a
+    // change of schedule changes the FP32 rounding of J, so it has to pay.
+    int best = 0;
+    for (int k = 1; k < n_all; ++k)
+        if (best_ms[k] < best_ms[best] && best_ms[k] < 0.98f * best_ms[0]) best = k;
+    plan->col_sched = best / nz;
+    plan->z_sched = best % nz;
+    if (ms_out) std::memcpy(ms_out, best_ms, sizeof(float) * (size_t)n_all);
+    if (col) *col = plan->col_sched;
+    if (z) *z = plan->z_sched;
+    return AMBER_OK;
+}
+
 size_t amber_halo_workspace_bytes(amber_plan plan) {
     if (!plan) return 0;
     return ws_layout(plan->n, 2, true).total;

@@ -18,6 +18,7 @@
 // with the same coalesced pattern.  Twiddles come from an FP64-generated table;
 // the in-register DFT constants are exact compile-time values.
 #include <cmath>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -215,21 +216,41 @@ __device__ __forceinline__ void fft_2step(float2* v, int t, float2* lds, const f
     }
 }
 
-// Per-N launch shapes.
-//   column passes : L = N split N1 x N2, tiles of C columns, C * N1 threads
-//   z passes      : M = N/2 split M1 x M2, ZL lines per block, ZL * M1 threads
+// Launch schedules.  A column pass splits L = N into N1 x N2 and takes tiles
+// of C columns (C * N1 threads); a z pass splits M = N/2 into M1 x M2 and takes
+// ZL lines per block (ZL * M1 threads).  Each grid size has a list of
+// candidates; the first is the default and a plan may pick any of them (the
+// tuner times them on the device).  Every candidate keeps L1 | L2 with both
+// factors among the in-register DFT sizes.
+template <int N1_, int C_>
+struct ColS {
+    static constexpr int N1 = N1_, C = C_;
+};
+template <int M1_, int ZL_>
+struct ZS {
+    static constexpr int M1 = M1_, ZL = ZL_;
+};
+template <class... T>
+struct List {
+    static constexpr int size = sizeof...(T);
+};
 template <int N>
-struct Shape;
-template <> struct Shape<8>    { static constexpr int N1 = 2,  C = 4,  M1 = 2,  ZL = 64; };
-template <> struct Shape<16>   { static constexpr int N1 = 4,  C = 8,  M1 = 2,  ZL = 64; };
-template <> struct Shape<32>   { static constexpr int N1 = 4,  C = 16, M1 = 4,  ZL = 64; };
-template <> struct Shape<64>   { static constexpr int N1 = 8,  C = 32, M1 = 4,  ZL = 64; };
-template <> struct Shape<96>   { static constexpr int N1 = 4,  C = 16, M1 = 4,  ZL = 64; };
-template <> struct Shape<128>  { static constexpr int N1 = 8,  C = 32, M1 = 8,  ZL = 32; };
-template <> struct Shape<192>  { static constexpr int N1 = 8,  C = 32, M1 = 4,  ZL = 64; };
-template <> struct Shape<256>  { static constexpr int N1 = 16, C = 16, M1 = 8,  ZL = 32; };
-template <> struct Shape<512>  { static constexpr int N1 = 16, C = 16, M1 = 16, ZL = 16; };
-template <> struct Shape<1024> { static constexpr int N1 = 32, C = 8,  M1 = 16, ZL = 16; };
+struct Scheds;
+template <> struct Scheds<8>    { using col = List<ColS<2, 4>>;   using z = List<ZS<2, 64>>; };
+template <> struct Scheds<16>   { using col = List<ColS<4, 8>>;   using z = List<ZS<2, 64>>; };
+template <> struct Scheds<32>   { using col = List<ColS<4, 16>>;  using z = List<ZS<4, 64>>; };
+template <> struct Scheds<64>   { using col = List<ColS<8, 32>>;  using z = List<ZS<4, 64>>; };
+template <> struct Scheds<96>   { using col = List<ColS<4, 16>>;  using z = List<ZS<4, 64>>; };
+template <> struct Scheds<128>  { using col = List<ColS<8, 32>, ColS<8, 16>, ColS<4, 32>>;
+                                  using z = List<ZS<8, 32>, ZS<4, 64>, ZS<8, 64>>; };
+template <> struct Scheds<192>  { using col = List<ColS<8, 32>, ColS<8, 16>, ColS<8, 48>>;
+                                  using z = List<ZS<4, 64>, ZS<4, 32>, ZS<4, 16>>; };
+template <> struct Scheds<256>  { using col = List<ColS<16, 16>, ColS<8, 32>, ColS<16, 8>>;
+                                  using z = List<ZS<8, 32>, ZS<4, 64>, ZS<8, 16>>; };
+template <> struct Scheds<512>  { using col = List<ColS<16, 16>, ColS<16, 8>, ColS<16, 32>>;
+                                  using z = List<ZS<16, 16>, ZS<8, 32>, ZS<16, 8>>; };
+template <> struct Scheds<1024> { using col = List<ColS<32, 8>, ColS<32, 4>, ColS<32, 16>>;
+                                  using z = List<ZS<16, 16>, ZS<16, 8>, ZS<16, 32>>; };
 
 // Tile geometry of a column pass: element (row r, column c) of tile (ta, tb)
 // is at ta * sa + tb * sb + r * row + c * col (complex elements).
@@ -259,11 +280,11 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned grid) {
 // Column pass.  MODE 0: one transform (INV selects the direction).
 // MODE 1: forward transform, multiply by Khat(|k|)/N^3, inverse transform.
 // MODE 2: the input is already transformed along x: multiply, inverse.
-template <int N, int MODE, bool INV>
-__global__ __launch_bounds__(Shape<N>::C * Shape<N>::N1, 2) void k_fft_cols(
+template <int N, class CS, int MODE, bool INV>
+__global__ __launch_bounds__(CS::C * CS::N1, 2) void k_fft_cols(
     const float2* __restrict__ in, float2* __restrict__ out, const float2* __restrict__ tw,
     ColGeom g, MulArgs m) {
-    constexpr int N1 = Shape<N>::N1, C = Shape<N>::C, N2 = N / N1;
+    constexpr int N1 = CS::N1, C = CS::C, N2 = N / N1;
     __shared__ float2 lds[N1 * (N2 + 1) * C];
     const int tid = threadIdx.x;
     const int c = tid % C, t = tid / C;
@@ -309,11 +330,11 @@ __global__ __launch_bounds__(Shape<N>::C * Shape<N>::N1, 2) void k_fft_cols(
 // the Nyquist value in nyq).  Packs x[2n] + i x[2n+1], does an N/2-point FFT
 // and separates even and odd halves:
 //   X[k] = (Z[k] + conj Z[M-k])/2 - i W_N^k (Z[k] - conj Z[M-k])/2.
-template <int N>
-__global__ __launch_bounds__(Shape<N>::ZL * Shape<N>::M1) void k_fft_z_r2c(
+template <int N, class ZSc>
+__global__ __launch_bounds__(ZSc::ZL * ZSc::M1) void k_fft_z_r2c(
     const float* __restrict__ src, float2* __restrict__ main_out, float2* __restrict__ nyq_out,
     const float2* __restrict__ tw, long long n_lines) {
-    constexpr int M = N / 2, M1 = Shape<N>::M1, M2 = M / M1, ZL = Shape<N>::ZL;
+    constexpr int M = N / 2, M1 = ZSc::M1, M2 = M / M1, ZL = ZSc::ZL;
     constexpr int LS = M1 * (M2 + 1);  // per-line LDS stride (>= M + 1)
     __shared__ float2 lds[ZL * LS];
     const int tid = threadIdx.x;
@@ -350,11 +371,11 @@ __global__ __launch_bounds__(Shape<N>::ZL * Shape<N>::M1) void k_fft_z_r2c(
 // z pass, complex to real (unnormalised inverse):
 //   Z'[k] = (X[k] + conj X[M-k]) + i W_N^-k (X[k] - conj X[M-k]),
 //   z = IDFT_M(Z'),  x[2n] = Re z[n], x[2n+1] = Im z[n].
-template <int N>
-__global__ __launch_bounds__(Shape<N>::ZL * Shape<N>::M1) void k_fft_z_c2r(
+template <int N, class ZSc>
+__global__ __launch_bounds__(ZSc::ZL * ZSc::M1) void k_fft_z_c2r(
     const float2* __restrict__ main_in, const float2* __restrict__ nyq_in, float* __restrict__ dst,
     const float2* __restrict__ tw, long long n_lines) {
-    constexpr int M = N / 2, M1 = Shape<N>::M1, M2 = M / M1, ZL = Shape<N>::ZL;
+    constexpr int M = N / 2, M1 = ZSc::M1, M2 = M / M1, ZL = ZSc::ZL;
     constexpr int LS = M1 * (M2 + 1);
     __shared__ float2 lds[ZL * LS];
     const int tid = threadIdx.x;
@@ -393,10 +414,10 @@ __global__ __launch_bounds__(Shape<N>::ZL * Shape<N>::M1) void k_fft_z_c2r(
     }
 }
 
-template <int N>
+template <int N, class CS, class ZSc>
 int run_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp, int n_lmfp,
                   float* const* d_J, unsigned char* ws, const WsLayout& L, hipStream_t s) {
-    constexpr int H = N / 2, C = Shape<N>::C, N1 = Shape<N>::N1, ZL = Shape<N>::ZL, M1 = Shape<N>::M1;
+    constexpr int H = N / 2, C = CS::C, N1 = CS::N1, ZL = ZSc::ZL, M1 = ZSc::M1;
     static_assert(H % C == 0 && N % C == 0, "tile width must divide the spectrum rows");
     const long long n_lines = (long long)N * N;
     float2* spec_a = reinterpret_cast<float2*>(ws + L.spec_a);
@@ -415,9 +436,9 @@ int run_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp
     const unsigned g_main = (unsigned)N * (H / C), g_nyq = (unsigned)(N / C);
     const MulArgs none{0.f, 0.f, 0.f, 0};
 
-    AMBER_LAUNCH(p, "fft_z_r2c", (k_fft_z_r2c<N>), dim3(zgrid), zblk, s, d_src, spec_a, nyq_a, tw, n_lines);
-    AMBER_LAUNCH(p, "fft_y", (k_fft_cols<N, 0, false>), dim3(g_main), cblk, s, spec_a, spec_a, tw, y_main, none);
-    AMBER_LAUNCH(p, "fft_nyq_y", (k_fft_cols<N, 0, false>), dim3(g_nyq), cblk, s, nyq_a, nyq_a, tw, y_nyq, none);
+    AMBER_LAUNCH(p, "fft_z_r2c", (k_fft_z_r2c<N, ZSc>), dim3(zgrid), zblk, s, d_src, spec_a, nyq_a, tw, n_lines);
+    AMBER_LAUNCH(p, "fft_y", (k_fft_cols<N, CS, 0, false>), dim3(g_main), cblk, s, spec_a, spec_a, tw, y_main, none);
+    AMBER_LAUNCH(p, "fft_nyq_y", (k_fft_cols<N, CS, 0, false>), dim3(g_nyq), cblk, s, nyq_a, nyq_a, tw, y_nyq, none);
     for (int i = 0; i < n_lmfp; ++i) {
         float2* so = (n_lmfp == 1) ? spec_a : spec_b;
         float2* no = (n_lmfp == 1) ? nyq_a : nyq_b;
@@ -425,22 +446,64 @@ int run_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp
         const float sc = (float)(1.0 / ((double)N * N * N));
         const MulArgs mm{k0, (float)l_mfp[i], sc, 0};
         const MulArgs mn{k0, (float)l_mfp[i], sc, 1};
-        AMBER_LAUNCH(p, "fft_x_mul", (k_fft_cols<N, 1, false>), dim3(g_main), cblk, s, spec_a, so, tw, x_main, mm);
-        AMBER_LAUNCH(p, "fft_nyq_x_mul", (k_fft_cols<N, 1, false>), dim3(g_nyq), cblk, s, nyq_a, no, tw, x_nyq, mn);
-        AMBER_LAUNCH(p, "fft_y_inv", (k_fft_cols<N, 0, true>), dim3(g_main), cblk, s, so, so, tw, y_main, none);
-        AMBER_LAUNCH(p, "fft_nyq_y_inv", (k_fft_cols<N, 0, true>), dim3(g_nyq), cblk, s, no, no, tw, y_nyq, none);
-        AMBER_LAUNCH(p, "fft_z_c2r", (k_fft_z_c2r<N>), dim3(zgrid), zblk, s, so, no, d_J[i], tw, n_lines);
+        AMBER_LAUNCH(p, "fft_x_mul", (k_fft_cols<N, CS, 1, false>), dim3(g_main), cblk, s, spec_a, so, tw, x_main, mm);
+        AMBER_LAUNCH(p, "fft_nyq_x_mul", (k_fft_cols<N, CS, 1, false>), dim3(g_nyq), cblk, s, nyq_a, no, tw, x_nyq, mn);
+        AMBER_LAUNCH(p, "fft_y_inv", (k_fft_cols<N, CS, 0, true>), dim3(g_main), cblk, s, so, so, tw, y_main, none);
+        AMBER_LAUNCH(p, "fft_nyq_y_inv", (k_fft_cols<N, CS, 0, true>), dim3(g_nyq), cblk, s, no, no, tw, y_nyq, none);
+        AMBER_LAUNCH(p, "fft_z_c2r", (k_fft_z_c2r<N, ZSc>), dim3(zgrid), zblk, s, so, no, d_J[i], tw, n_lines);
     }
     AMBER_HIP_CHECK(hipGetLastError());
     return AMBER_OK;
 }
 
+
+// Runs f(integral_constant<N>, column schedule, z schedule) for the plan's grid
+// size and chosen candidates.
+template <class F, class T0, class... T>
+int pick(List<T0, T...>, int idx, F&& f) {
+    if (idx == 0) return f(T0{});
+    if constexpr (sizeof...(T) > 0) {
+        return pick(List<T...>{}, idx - 1, f);
+    } else {
+        return AMBER_E_ARG;
+    }
+}
+
+template <int N, class F>
+int with_scheds(int col, int z, F&& f) {
+    return pick(typename Scheds<N>::col{}, col, [&](auto cs) {
+        return pick(typename Scheds<N>::z{}, z, [&](auto zs) { return f(std::integral_constant<int, N>{}, cs, zs); });
+    });
+}
+
+template <class F>
+int with_size(int n, F&& f) {
+    switch (n) {
+        case 8: return f(std::integral_constant<int, 8>{});
+        case 16: return f(std::integral_constant<int, 16>{});
+        case 32: return f(std::integral_constant<int, 32>{});
+        case 64: return f(std::integral_constant<int, 64>{});
+        case 96: return f(std::integral_constant<int, 96>{});
+        case 128: return f(std::integral_constant<int, 128>{});
+        case 192: return f(std::integral_constant<int, 192>{});
+        case 256: return f(std::integral_constant<int, 256>{});
+        case 512: return f(std::integral_constant<int, 512>{});
+        case 1024: return f(std::integral_constant<int, 1024>{});
+        default: return AMBER_E_SIZE;
+    }
+}
+
+template <class F>
+int dispatch(const amber_plan_s* p, F&& f) {
+    return with_size(p->n, [&](auto n) { return with_scheds<decltype(n)::value>(p->col_sched, p->z_sched, f); });
+}
+
 }  // namespace
 
 // Forward real 3D FFT only (unnormalised): main[x][y][kz < N/2] and nyq[x][y].
-template <int N>
+template <int N, class CS, class ZSc>
 int run_forward(const amber_plan_s* p, const float* d_src, float2* spec, float2* nyq, hipStream_t s) {
-    constexpr int H = N / 2, C = Shape<N>::C, N1 = Shape<N>::N1, ZL = Shape<N>::ZL, M1 = Shape<N>::M1;
+    constexpr int H = N / 2, C = CS::C, N1 = CS::N1, ZL = ZSc::ZL, M1 = ZSc::M1;
     const long long n_lines = (long long)N * N;
     const float2* tw = p->d_tw;
     const dim3 zblk(ZL * M1), cblk(C * N1);
@@ -451,39 +514,29 @@ int run_forward(const amber_plan_s* p, const float* d_src, float2* spec, float2*
     const ColGeom x_nyq{N, 1, 0, C, N / C};
     const unsigned g_main = (unsigned)N * (H / C), g_nyq = (unsigned)(N / C);
     const MulArgs none{0.f, 0.f, 0.f, 0};
-    AMBER_LAUNCH(p, "fft_z_r2c", (k_fft_z_r2c<N>), dim3(zgrid), zblk, s, d_src, spec, nyq, tw, n_lines);
-    AMBER_LAUNCH(p, "fft_y", (k_fft_cols<N, 0, false>), dim3(g_main), cblk, s, spec, spec, tw, y_main, none);
-    AMBER_LAUNCH(p, "fft_nyq_y", (k_fft_cols<N, 0, false>), dim3(g_nyq), cblk, s, nyq, nyq, tw, y_nyq, none);
-    AMBER_LAUNCH(p, "fft_x", (k_fft_cols<N, 0, false>), dim3(g_main), cblk, s, spec, spec, tw, x_main, none);
-    AMBER_LAUNCH(p, "fft_nyq_x", (k_fft_cols<N, 0, false>), dim3(g_nyq), cblk, s, nyq, nyq, tw, x_nyq, none);
+    AMBER_LAUNCH(p, "fft_z_r2c", (k_fft_z_r2c<N, ZSc>), dim3(zgrid), zblk, s, d_src, spec, nyq, tw, n_lines);
+    AMBER_LAUNCH(p, "fft_y", (k_fft_cols<N, CS, 0, false>), dim3(g_main), cblk, s, spec, spec, tw, y_main, none);
+    AMBER_LAUNCH(p, "fft_nyq_y", (k_fft_cols<N, CS, 0, false>), dim3(g_nyq), cblk, s, nyq, nyq, tw, y_nyq, none);
+    AMBER_LAUNCH(p, "fft_x", (k_fft_cols<N, CS, 0, false>), dim3(g_main), cblk, s, spec, spec, tw, x_main, none);
+    AMBER_LAUNCH(p, "fft_nyq_x", (k_fft_cols<N, CS, 0, false>), dim3(g_nyq), cblk, s, nyq, nyq, tw, x_nyq, none);
     AMBER_HIP_CHECK(hipGetLastError());
     return AMBER_OK;
 }
 
 int fft_forward(const amber_plan_s* p, const float* d_src, float2* spec, float2* nyq, hipStream_t s) {
-    switch (p->n) {
-        case 8: return run_forward<8>(p, d_src, spec, nyq, s);
-        case 16: return run_forward<16>(p, d_src, spec, nyq, s);
-        case 32: return run_forward<32>(p, d_src, spec, nyq, s);
-        case 64: return run_forward<64>(p, d_src, spec, nyq, s);
-        case 96: return run_forward<96>(p, d_src, spec, nyq, s);
-        case 128: return run_forward<128>(p, d_src, spec, nyq, s);
-        case 192: return run_forward<192>(p, d_src, spec, nyq, s);
-        case 256: return run_forward<256>(p, d_src, spec, nyq, s);
-        case 512: return run_forward<512>(p, d_src, spec, nyq, s);
-        case 1024: return run_forward<1024>(p, d_src, spec, nyq, s);
-        default: return AMBER_E_SIZE;
-    }
+    return dispatch(p, [&](auto n, auto cs, auto zs) {
+        return run_forward<decltype(n)::value, decltype(cs), decltype(zs)>(p, d_src, spec, nyq, s);
+    });
 }
 
 // J_l from a spectrum already transformed along all three axes (main + Nyquist
 // plane): per l_mfp, multiply by Khat/N^3 and inverse x in one pass (into the
 // scratch spectrum when there are several l_mfp, in place otherwise), inverse y,
 // complex-to-real.
-template <int N>
+template <int N, class CS, class ZSc>
 int run_from_spectrum(const amber_plan_s* p, float2* spec, float2* nyq, const double* l_mfp, int n_lmfp,
                       float* const* d_J, float2* spec_tmp, float2* nyq_tmp, hipStream_t s) {
-    constexpr int H = N / 2, C = Shape<N>::C, N1 = Shape<N>::N1, ZL = Shape<N>::ZL, M1 = Shape<N>::M1;
+    constexpr int H = N / 2, C = CS::C, N1 = CS::N1, ZL = ZSc::ZL, M1 = ZSc::M1;
     const long long n_lines = (long long)N * N;
     const float2* tw = p->d_tw;
     const dim3 zblk(ZL * M1), cblk(C * N1);
@@ -501,11 +554,11 @@ int run_from_spectrum(const amber_plan_s* p, float2* spec, float2* nyq, const do
         const float sc = (float)(1.0 / ((double)N * N * N));
         const MulArgs mm{k0, (float)l_mfp[i], sc, 0};
         const MulArgs mn{k0, (float)l_mfp[i], sc, 1};
-        AMBER_LAUNCH(p, "fft_x_mul_inv", (k_fft_cols<N, 2, false>), dim3(g_main), cblk, s, spec, so, tw, x_main, mm);
-        AMBER_LAUNCH(p, "fft_nyq_x_mul_inv", (k_fft_cols<N, 2, false>), dim3(g_nyq), cblk, s, nyq, no, tw, x_nyq, mn);
-        AMBER_LAUNCH(p, "fft_y_inv", (k_fft_cols<N, 0, true>), dim3(g_main), cblk, s, so, so, tw, y_main, none);
-        AMBER_LAUNCH(p, "fft_nyq_y_inv", (k_fft_cols<N, 0, true>), dim3(g_nyq), cblk, s, no, no, tw, y_nyq, none);
-        AMBER_LAUNCH(p, "fft_z_c2r", (k_fft_z_c2r<N>), dim3(zgrid), zblk, s, so, no, d_J[i], tw, n_lines);
+        AMBER_LAUNCH(p, "fft_x_mul_inv", (k_fft_cols<N, CS, 2, false>), dim3(g_main), cblk, s, spec, so, tw, x_main, mm);
+        AMBER_LAUNCH(p, "fft_nyq_x_mul_inv", (k_fft_cols<N, CS, 2, false>), dim3(g_nyq), cblk, s, nyq, no, tw, x_nyq, mn);
+        AMBER_LAUNCH(p, "fft_y_inv", (k_fft_cols<N, CS, 0, true>), dim3(g_main), cblk, s, so, so, tw, y_main, none);
+        AMBER_LAUNCH(p, "fft_nyq_y_inv", (k_fft_cols<N, CS, 0, true>), dim3(g_nyq), cblk, s, no, no, tw, y_nyq, none);
+        AMBER_LAUNCH(p, "fft_z_c2r", (k_fft_z_c2r<N, ZSc>), dim3(zgrid), zblk, s, so, no, d_J[i], tw, n_lines);
     }
     AMBER_HIP_CHECK(hipGetLastError());
     return AMBER_OK;
@@ -513,34 +566,41 @@ int run_from_spectrum(const amber_plan_s* p, float2* spec, float2* nyq, const do
 
 int fft_from_spectrum(const amber_plan_s* p, float2* spec, float2* nyq, const double* l_mfp, int n_lmfp,
                       float* const* d_J, float2* spec_tmp, float2* nyq_tmp, hipStream_t s) {
-    switch (p->n) {
-        case 8: return run_from_spectrum<8>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
-        case 16: return run_from_spectrum<16>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
-        case 32: return run_from_spectrum<32>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
-        case 64: return run_from_spectrum<64>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
-        case 96: return run_from_spectrum<96>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
-        case 128: return run_from_spectrum<128>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
-        case 192: return run_from_spectrum<192>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
-        case 256: return run_from_spectrum<256>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
-        case 512: return run_from_spectrum<512>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
-        case 1024: return run_from_spectrum<1024>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp, nyq_tmp, s);
-        default: return AMBER_E_SIZE;
-    }
+    return dispatch(p, [&](auto n, auto cs, auto zs) {
+        return run_from_spectrum<decltype(n)::value, decltype(cs), decltype(zs)>(p, spec, nyq, l_mfp, n_lmfp, d_J, spec_tmp,
+                                                                                   nyq_tmp, s);
+    });
 }
 
 int fft_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp, int n_lmfp,
                   float* const* d_J, unsigned char* ws, const WsLayout& L, hipStream_t s) {
-    switch (p->n) {
-        case 8: return run_radiation<8>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
-        case 16: return run_radiation<16>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
-        case 32: return run_radiation<32>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
-        case 64: return run_radiation<64>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
-        case 96: return run_radiation<96>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
-        case 128: return run_radiation<128>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
-        case 192: return run_radiation<192>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
-        case 256: return run_radiation<256>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
-        case 512: return run_radiation<512>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
-        case 1024: return run_radiation<1024>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
-        default: return AMBER_E_SIZE;
-    }
+    return dispatch(p, [&](auto n, auto cs, auto zs) {
+        return run_radiation<decltype(n)::value, decltype(cs), decltype(zs)>(p, d_src, l_mfp, n_lmfp, d_J, ws, L, s);
+    });
+}
+
+int fft_schedule_count(int n, int* n_col, int* n_z) {
+    return with_size(n, [&](auto nc) {
+        using S = Scheds<decltype(nc)::value>;
+        *n_col = S::col::size;
+        *n_z = S::z::size;
+        return AMBER_OK;
+    });
+}
+
+int fft_schedule_info(int n, int kind, int idx, int* a, int* b) {
+    return with_size(n, [&](auto nc) {
+        using S = Scheds<decltype(nc)::value>;
+        if (kind == 0) return pick(typename S::col{}, idx, [&](auto cs) {
+            *a = decltype(cs)::N1;
+            *b = decltype(cs)::C;
+            return AMBER_OK;
+        });
+        if (kind == 1) return pick(typename S::z{}, idx, [&](auto zs) {
+            *a = decltype(zs)::M1;
+            *b = decltype(zs)::ZL;
+            return AMBER_OK;
+        });
+        return AMBER_E_ARG;
+    });
 }

@@ -23,6 +23,8 @@ struct amber_plan_s {
     double box_len = 0.0;  // box side
     int device = -1;
     float2* d_tw = nullptr;  // tw[j] = exp(-2 pi i j / n), j < n, FP64-rounded to FP32
+    int col_sched = 0;       // FFT column-pass candidate (0: default)
+    int z_sched = 0;         // FFT z-pass candidate (0: default)
     Profiler* prof = nullptr;
 };
 
@@ -139,6 +141,12 @@ int fft_forward(const amber_plan_s* p, const float* d_src, float2* spec, float2*
 // spectrum is kept when n_lmfp > 1 (the products go through spec_tmp).
 int fft_from_spectrum(const amber_plan_s* p, float2* spec, float2* nyq, const double* l_mfp, int n_lmfp,
                       float* const* d_J, float2* spec_tmp, float2* nyq_tmp, hipStream_t s);
+
+// FFT launch candidates compiled for grid size n (fft.hip): how many for the
+// column and z passes, and the split of candidate idx (kind 0: N1 threads per
+// column and C columns per tile; kind 1: M1 threads per line and ZL lines).
+int fft_schedule_count(int n, int* n_col, int* n_z);
+int fft_schedule_info(int n, int kind, int idx, int* a, int* b);
 
 // Edge of the cubic mesh tiles the halo deposit bins by; grids it does not
 // divide use the direct (atomic) deposit.

@@ -135,3 +135,57 @@ def test_serving_busy_time_is_the_union_of_batch_intervals():
     assert _union([]) == 0.0
     assert _union([(0.0, 1.0), (0.5, 2.0), (3.0, 4.0)]) == pytest.approx(3.0)
     assert _union([(1.0, 2.0), (0.0, 5.0)]) == pytest.approx(5.0)
+
+
+# In-register DFT sizes the FFT passes support (products of 2, 3 and 4 up to 32).
+_DFT_SIZES = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32}
+
+
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 96, 128, 192, 256, 512, 1024])
+def test_fft_schedule_candidates_are_valid_splits(n):
+    """Every compiled candidate splits its transform as L1 x L2 with L1 | L2,
+    both among the in-register DFT sizes, tiles that cover the spectrum rows
+    exactly and blocks within 1024 threads (host-only queries)."""
+    import paper_2109_10375_amd as amber
+    cand = amber.fft_schedules(n)
+    assert len(cand["col"]) >= 1 and len(cand["z"]) >= 1
+    assert len(set(cand["col"])) == len(cand["col"]) and len(set(cand["z"])) == len(cand["z"])
+    for n1, c in cand["col"]:
+        n2 = n // n1
+        assert n1 * n2 == n and n2 % n1 == 0 and n1 in _DFT_SIZES and n2 in _DFT_SIZES
+        assert (n // 2) % c == 0 and n1 * c <= 1024
+    for m1, zl in cand["z"]:
+        m = n // 2
+        m2 = m // m1
+        assert m1 * m2 == m and m2 % m1 == 0 and m1 in _DFT_SIZES and m2 in _DFT_SIZES
+        assert m1 * zl <= 1024
+    a, b = ctypes.c_int(), ctypes.c_int()
+    L = amber.lib()
+    assert L.amber_fft_schedule_info(n, 0, len(cand["col"]), ctypes.byref(a), ctypes.byref(b)) == -1
+    assert L.amber_fft_schedule_info(n, 1, len(cand["z"]), ctypes.byref(a), ctypes.byref(b)) == -1
+    assert L.amber_fft_schedule_info(n, 2, 0, ctypes.byref(a), ctypes.byref(b)) == -1
+    assert L.amber_fft_schedule_info(n, 0, -1, ctypes.byref(a), ctypes.byref(b)) == -1
+    assert L.amber_fft_schedules(n + 1, ctypes.byref(a), ctypes.byref(b)) == -2
+
+
+def test_tune_cache_round_trip_and_stale_entries(tmp_path):
+    from paper_2109_10375_amd import tune
+    path = str(tmp_path / "sub" / "tune.json")
+    assert tune.load(path) == {}
+    cand = {"col": [(32, 8), (32, 4)], "z": [(16, 16), (16, 8)]}
+    key = tune.entry_key("gfx950|MI355X|cu256", 1024)
+    entry = {"col": 1, "z": 0, "col_split": [32, 4], "z_split": [16, 16], "ms": [[1.0, 2.0], [0.5, 3.0]], "reps": 5}
+    tune.store(path, key, entry)
+    tune.store(path, tune.entry_key("gfx950|MI355X|cu256", 512), dict(entry, col=0, col_split=[32, 8]))
+    got = tune.load(path)
+    assert got[key] == entry and len(got) == 2
+    assert tune.valid_entry(got[key], cand)
+    assert not tune.valid_entry(dict(entry, col=2), cand)                 # no such candidate
+    assert not tune.valid_entry(dict(entry, col_split=[32, 16]), cand)    # candidate list changed
+    assert not tune.valid_entry({"col": 0}, cand)
+    with open(path, "w") as f:
+        f.write("{not json")
+    assert tune.load(path) == {}
+    with open(path, "w") as f:
+        f.write('{"version": 0, "entries": {}}')
+    assert tune.load(path) == {}
