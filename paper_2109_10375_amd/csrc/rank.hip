@@ -70,8 +70,16 @@ __device__ __forceinline__ unsigned digit_excl_scan(unsigned v, unsigned* sh /* 
 __global__ __launch_bounds__(kHistThreads) void k_hist(const float* __restrict__ J, long long n, Ctrl* ctrl,
                                                        unsigned* __restrict__ lb0, long long lb_words) {
     __shared__ unsigned h[kHistWaves][4][256];
+    // The top digit (sign and exponent) takes a handful of values, so one
+    // LDS word per value would take the atomics of most lanes at once: it is
+    // counted per lane instead, in 16-bit halves (lanes 2k and 2k+1 share a
+    // word, the block's waves share the words: at most kHistWaves * 16 keys
+    // per round per half, which the host keeps below 2^16).
+    __shared__ unsigned top[256][32];
     const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < kHistWaves * 4 * 256; i += kHistThreads) (&h[0][0][0])[i] = 0;
+    for (int i = threadIdx.x; i < 256 * 32; i += kHistThreads) (&top[0][0])[i] = 0;
     for (long long i = (long long)blockIdx.x * kHistThreads + threadIdx.x; i < lb_words;
          i += (long long)gridDim.x * kHistThreads)
         lb0[i] = 0;
@@ -100,29 +108,21 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const float* __restrict__
                     atomicAdd(&h[wave][0][key & 255u], 1u);
                     atomicAdd(&h[wave][1][(key >> 8) & 255u], 1u);
                     atomicAdd(&h[wave][2][(key >> 16) & 255u], 1u);
+                    atomicAdd(&top[key >> 24][lane >> 1], (lane & 1) ? 65536u : 1u);
                 }
-                // The top digit (sign and exponent) takes few values among
-                // neighbouring cells: the two most common ones in the wave
-                // (in practice) are counted once each by the lowest lane
-                // holding them, any other lane adds its own.
-                const unsigned d3 = key >> 24;
-                const int lane = threadIdx.x & 63;
-                unsigned long long left = __ballot(live);
-#pragma unroll
-                for (int round = 0; round < 2; ++round) {
-                    if (left) {  // wave-uniform
-                        const int leader = __ffsll((long long)left) - 1;
-                        const unsigned dv = __builtin_amdgcn_readlane(d3, leader);
-                        const unsigned long long same = __ballot(live && d3 == dv);
-                        if (lane == leader) atomicAdd(&h[wave][3][dv], (unsigned)__popcll(same));
-                        left &= ~same;
-                    }
-                }
-                if ((left >> lane) & 1ull) atomicAdd(&h[wave][3][d3], 1u);
             }
         }
     }
-    if (__any(nan) && (threadIdx.x & 63) == 0) atomicOr(&ctrl->status, AMBER_STATUS_NAN_J);
+    if (__any(nan) && lane == 0) atomicOr(&ctrl->status, AMBER_STATUS_NAN_J);
+    __syncthreads();
+    for (int d = threadIdx.x; d < 256; d += kHistThreads) {
+        unsigned c = 0;
+        for (int j = 0; j < 32; ++j) {
+            const unsigned x = top[d][j];
+            c += (x & 0xffffu) + (x >> 16);
+        }
+        h[0][3][d] += c;
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < 4 * 256; i += kHistThreads) {
         unsigned s = 0;
@@ -454,6 +454,9 @@ int rank_sort(const amber_plan_s* p, const float* d_J, const float* d_w, unsigne
     AMBER_LAUNCH(p, "rank_init", k_ctrl_init, dim3(1), dim3(256), s, ctrl);
     const unsigned hist_blocks =
         (unsigned)std::min<long long>(2048, (n + kHistThreads * 16 - 1) / (kHistThreads * 16));
+    // the histogram's per-lane top-digit counters are 16 bits wide
+    const long long hist_step = (long long)hist_blocks * kHistThreads * 4;
+    if ((long long)kHistWaves * 16 * ((n / 4 + hist_step - 1) / hist_step) > 65535) return AMBER_E_SIZE;
     AMBER_LAUNCH(p, "rank_hist", k_hist, dim3(hist_blocks), dim3(kHistThreads), s, d_J, n, ctrl, lb[0], n_tiles * 256);
     AMBER_LAUNCH(p, "rank_digit_offsets", k_digit_offsets, dim3(1), dim3(256), s, ctrl);
     uint32_t* final_vals = d_perm_out ? d_perm_out : vals[0];
