@@ -260,11 +260,35 @@ struct ColGeom {
 };
 
 struct MulArgs {
-    float k0;     // 2 pi / box_len
-    float lmfp;
-    float scale;  // 1 / N^3
+    float c2;     // (2 pi l_mfp / box_len)^2: x^2 = c2 |m~|^2 with x = k l_mfp
+    float ls;     // l_mfp / N^3
     int nyq;      // 1: the Nyquist plane (kz = N/2, columns are ky)
 };
+
+MulArgs mul_args(double box_len, double l_mfp, int n, int nyq) {
+    const double kl = 2.0 * kPi * l_mfp / box_len;
+    return MulArgs{(float)(kl * kl), (float)(l_mfp / ((double)n * n * n)), nyq};
+}
+
+// Khat(k)/N^3 = (l/N^3) g(x), g(x) = atan(x)/x, x = k l, from x^2 = c2 |m~|^2.
+// On x <= 1, g = P(x^2); above, atan(x) = pi/2 - atan(1/x) gives
+// g(x) = r (pi/2 - r P(r^2)) with r = 1/x.  P is a degree-9 polynomial with
+// P(0) = 1, fitted to atan(sqrt t)/sqrt t on [0, 1] for relative error
+// (csrc/fit_atan.py; 8e-8 relative in FP32); the reciprocal and reciprocal
+// square root are the hardware's (about 1 ulp).
+__device__ __forceinline__ float khat_scaled(float x2, float ls) {
+    constexpr float kP[10] = {-1.744857524e-03f, 1.069426350e-02f, -3.076297976e-02f, 5.753647164e-02f,
+                              -8.378560096e-02f, 1.094356626e-01f, -1.426257640e-01f, 1.999839097e-01f,
+                              -3.333329260e-01f, 1.000000000e+00f};
+    const bool big = x2 > 1.0f;
+    const float t = big ? __builtin_amdgcn_rcpf(x2) : x2;
+    float p = kP[0];
+#pragma unroll
+    for (int i = 1; i < 10; ++i) p = __builtin_fmaf(p, t, kP[i]);
+    const float r = __builtin_amdgcn_rsqf(big ? x2 : 1.0f);
+    const float g = big ? r * (1.57079632679489662f - r * p) : p;
+    return g * ls;
+}
 
 __device__ __forceinline__ int signed_freq(int m, int n) { return (2 * m <= n) ? m : m - n; }
 
@@ -312,9 +336,7 @@ __global__ __launch_bounds__(CS::C * CS::N1, 2) void k_fft_cols(
 #pragma unroll
         for (int j = 0; j < N2; ++j) {
             const int sx = signed_freq(t + N1 * j, N);
-            const float kk = m.k0 * sqrtf((float)(sx * sx + s2yz));
-            const float K = (kk > 0.0f) ? atanf(kk * m.lmfp) / kk : m.lmfp;
-            v[j] = cscale(v[j], K * m.scale);
+            v[j] = cscale(v[j], khat_scaled(m.c2 * (float)(sx * sx + s2yz), m.ls));
         }
         fft_2step<N, N1, true, 1, (N2 + 1) * C, C>(v, t, col, tw);
     }
@@ -434,7 +456,7 @@ int run_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp
     const ColGeom x_main{(long long)N * H, 1, H, C, H / C};
     const ColGeom x_nyq{N, 1, 0, C, N / C};
     const unsigned g_main = (unsigned)N * (H / C), g_nyq = (unsigned)(N / C);
-    const MulArgs none{0.f, 0.f, 0.f, 0};
+    const MulArgs none{0.f, 0.f, 0};
 
     AMBER_LAUNCH(p, "fft_z_r2c", (k_fft_z_r2c<N, ZSc>), dim3(zgrid), zblk, s, d_src, spec_a, nyq_a, tw, n_lines);
     AMBER_LAUNCH(p, "fft_y", (k_fft_cols<N, CS, 0, false>), dim3(g_main), cblk, s, spec_a, spec_a, tw, y_main, none);
@@ -442,10 +464,8 @@ int run_radiation(const amber_plan_s* p, const float* d_src, const double* l_mfp
     for (int i = 0; i < n_lmfp; ++i) {
         float2* so = (n_lmfp == 1) ? spec_a : spec_b;
         float2* no = (n_lmfp == 1) ? nyq_a : nyq_b;
-        const float k0 = (float)(2.0 * kPi / p->box_len);
-        const float sc = (float)(1.0 / ((double)N * N * N));
-        const MulArgs mm{k0, (float)l_mfp[i], sc, 0};
-        const MulArgs mn{k0, (float)l_mfp[i], sc, 1};
+        const MulArgs mm = mul_args(p->box_len, l_mfp[i], N, 0);
+        const MulArgs mn = mul_args(p->box_len, l_mfp[i], N, 1);
         AMBER_LAUNCH(p, "fft_x_mul", (k_fft_cols<N, CS, 1, false>), dim3(g_main), cblk, s, spec_a, so, tw, x_main, mm);
         AMBER_LAUNCH(p, "fft_nyq_x_mul", (k_fft_cols<N, CS, 1, false>), dim3(g_nyq), cblk, s, nyq_a, no, tw, x_nyq, mn);
         AMBER_LAUNCH(p, "fft_y_inv", (k_fft_cols<N, CS, 0, true>), dim3(g_main), cblk, s, so, so, tw, y_main, none);
@@ -513,7 +533,7 @@ int run_forward(const amber_plan_s* p, const float* d_src, float2* spec, float2*
     const ColGeom x_main{(long long)N * H, 1, H, C, H / C};
     const ColGeom x_nyq{N, 1, 0, C, N / C};
     const unsigned g_main = (unsigned)N * (H / C), g_nyq = (unsigned)(N / C);
-    const MulArgs none{0.f, 0.f, 0.f, 0};
+    const MulArgs none{0.f, 0.f, 0};
     AMBER_LAUNCH(p, "fft_z_r2c", (k_fft_z_r2c<N, ZSc>), dim3(zgrid), zblk, s, d_src, spec, nyq, tw, n_lines);
     AMBER_LAUNCH(p, "fft_y", (k_fft_cols<N, CS, 0, false>), dim3(g_main), cblk, s, spec, spec, tw, y_main, none);
     AMBER_LAUNCH(p, "fft_nyq_y", (k_fft_cols<N, CS, 0, false>), dim3(g_nyq), cblk, s, nyq, nyq, tw, y_nyq, none);
@@ -546,14 +566,12 @@ int run_from_spectrum(const amber_plan_s* p, float2* spec, float2* nyq, const do
     const ColGeom x_main{(long long)N * H, 1, H, C, H / C};
     const ColGeom x_nyq{N, 1, 0, C, N / C};
     const unsigned g_main = (unsigned)N * (H / C), g_nyq = (unsigned)(N / C);
-    const MulArgs none{0.f, 0.f, 0.f, 0};
+    const MulArgs none{0.f, 0.f, 0};
     for (int i = 0; i < n_lmfp; ++i) {
         float2* so = (n_lmfp == 1) ? spec : spec_tmp;
         float2* no = (n_lmfp == 1) ? nyq : nyq_tmp;
-        const float k0 = (float)(2.0 * kPi / p->box_len);
-        const float sc = (float)(1.0 / ((double)N * N * N));
-        const MulArgs mm{k0, (float)l_mfp[i], sc, 0};
-        const MulArgs mn{k0, (float)l_mfp[i], sc, 1};
+        const MulArgs mm = mul_args(p->box_len, l_mfp[i], N, 0);
+        const MulArgs mn = mul_args(p->box_len, l_mfp[i], N, 1);
         AMBER_LAUNCH(p, "fft_x_mul_inv", (k_fft_cols<N, CS, 2, false>), dim3(g_main), cblk, s, spec, so, tw, x_main, mm);
         AMBER_LAUNCH(p, "fft_nyq_x_mul_inv", (k_fft_cols<N, CS, 2, false>), dim3(g_nyq), cblk, s, nyq, no, tw, x_nyq, mn);
         AMBER_LAUNCH(p, "fft_y_inv", (k_fft_cols<N, CS, 0, true>), dim3(g_main), cblk, s, so, so, tw, y_main, none);

@@ -189,3 +189,39 @@ def test_tune_cache_round_trip_and_stale_entries(tmp_path):
     with open(path, "w") as f:
         f.write('{"version": 0, "entries": {}}')
     assert tune.load(path) == {}
+
+
+def _kernel_poly_from_source():
+    src = open(os.path.join(ROOT, "paper_2109_10375_amd", "csrc", "fft.hip")).read()
+    body = re.search(r"constexpr float kP\[10\] = \{([^}]*)\}", src).group(1)
+    return np.array([float(x.strip().rstrip("f")) for x in body.split(",")], dtype=np.float32)
+
+
+def test_khat_polynomial_is_the_committed_fit_and_matches_arctan():
+    """The radiation kernel's atan(x)/x: the coefficients in fft.hip are those
+    csrc/fit_atan.py produces, and the kernel's evaluation (polynomial in x^2
+    on x <= 1, reflection r (pi/2 - r P(r^2)) above; reciprocal and reciprocal
+    square root emulated correctly rounded) agrees with numpy's arctan in FP64
+    to 3e-7 relative from x = 0 to 1e4."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "fit_atan", os.path.join(ROOT, "paper_2109_10375_amd", "csrc", "fit_atan.py"))
+    fit = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(fit)
+    kp = _kernel_poly_from_source()
+    assert np.array_equal(kp, fit.coefficients_f32()[::-1])
+    assert kp[-1] == np.float32(1.0)
+    x = np.concatenate([[0.0], np.geomspace(1e-6, 1e4, 400001)])
+    x2 = (x * x).astype(np.float32)
+    big = x2 > 1
+    t = np.where(big, (1.0 / np.where(big, x2, 1).astype(np.float64)).astype(np.float32), x2)
+    p = fit.horner_f32(kp[::-1], t).astype(np.float32)
+    r = (1.0 / np.sqrt(np.where(big, x2, 1).astype(np.float64))).astype(np.float32)
+    g_big = (r * (np.float32(np.pi / 2) - (r * p).astype(np.float32))).astype(np.float32)
+    g = np.where(big, g_big, p).astype(np.float64)
+    x64 = np.sqrt(x2.astype(np.float64))
+    ref = np.ones_like(x64)
+    nz = x64 > 0
+    ref[nz] = np.arctan(x64[nz]) / x64[nz]
+    rel = np.max(np.abs(g - ref) / ref)
+    assert rel < 3e-7, rel
