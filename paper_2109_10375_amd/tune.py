@@ -3,7 +3,7 @@
 The tuner itself is amber_plan_tune (C-ABI): it times every compiled
 (column pass, z pass) candidate pair of a plan on the device and keeps the
 fastest.  This module remembers that choice in a JSON file keyed by the device
-(architecture, name, compute units) and the grid size, so a later process on
+(architecture, compute units, memory size) and the grid size, so a later process on
 the same kind of GPU sets the schedule without timing again.  An entry whose
 recorded splits no longer match the library's candidate list is ignored and
 replaced.  The cache path is the `cache` argument, else the environment
@@ -24,10 +24,12 @@ CACHE_VERSION = 1
 
 
 def device_key(device: Optional[torch.device] = None) -> str:
-    """Identity of the GPU a schedule was timed on."""
+    """Identity of the GPU a schedule was timed on: architecture, compute
+    units and memory size (the marketing name is left out: some tools that
+    wrap a process report it empty)."""
     props = torch.cuda.get_device_properties(device if device is not None else torch.cuda.current_device())
     arch = getattr(props, "gcnArchName", "") or ""
-    return f"{arch}|{props.name}|cu{props.multi_processor_count}"
+    return f"{arch}|cu{props.multi_processor_count}|{props.total_memory >> 30}GiB"
 
 
 def entry_key(dev_key: str, n: int) -> str:

@@ -173,10 +173,10 @@ def test_tune_cache_round_trip_and_stale_entries(tmp_path):
     path = str(tmp_path / "sub" / "tune.json")
     assert tune.load(path) == {}
     cand = {"col": [(32, 8), (32, 4)], "z": [(16, 16), (16, 8)]}
-    key = tune.entry_key("gfx950|MI355X|cu256", 1024)
+    key = tune.entry_key("gfx950|cu256|288GiB", 1024)
     entry = {"col": 1, "z": 0, "col_split": [32, 4], "z_split": [16, 16], "ms": [[1.0, 2.0], [0.5, 3.0]], "reps": 5}
     tune.store(path, key, entry)
-    tune.store(path, tune.entry_key("gfx950|MI355X|cu256", 512), dict(entry, col=0, col_split=[32, 8]))
+    tune.store(path, tune.entry_key("gfx950|cu256|288GiB", 512), dict(entry, col=0, col_split=[32, 8]))
     got = tune.load(path)
     assert got[key] == entry and len(got) == 2
     assert tune.valid_entry(got[key], cand)
