@@ -168,26 +168,44 @@ __device__ __forceinline__ double growth_gap(double ks, double ns, double cn, do
     return m / M - X;
 }
 
+// Sign of the gap RN(m/M) - X at one node: 1 when it is > 0, 0 when <= 0,
+// -1 when unordered, the same as evaluating growth_gap and comparing.  With
+// M > 0 and X >= 0 it is decided without the division where it can be: one
+// fused multiply-add rounds m - X M once, so its sign is that of the exact
+// value; m <= X M gives RN(m/M) <= X, and m >= X' M, X' the next double above
+// X, gives RN(m/M) >= X' > X.  Only a quotient strictly between X and X'
+// (where the rounding of m/M decides) takes the division.
+__device__ __forceinline__ int growth_gap_sign(double ks, double ns, double cn, double cN, double G, double X) {
+#pragma clang fp contract(off)
+    const double one_m = 1.0 - G;
+    const double m = ks * one_m + G * cn;
+    const double M = ns * one_m + G * cN;
+    if (M > 0.0 && X >= 0.0) {
+        if (__builtin_fma(-X, M, m) <= 0.0) return 0;
+        const double Xs = __longlong_as_double(__double_as_longlong(X) + 1);
+        if (__builtin_fma(-Xs, M, m) >= 0.0) return 1;
+    }
+    const double g = m / M - X;
+    return g > 0.0 ? 1 : (g <= 0.0 ? 0 : -1);
+}
+
 __device__ double invert_growth(double ks, double ns, double cn, double cN, double a, double h, long long T,
                                 double z_top, const double* __restrict__ X, const double* __restrict__ G) {
 #pragma clang fp contract(off)
-    const double h0 = growth_gap(ks, ns, cn, cN, G[0], X[0]);
-    if (h0 > 0.0) return a;
-    const double hT = growth_gap(ks, ns, cn, cN, G[T], X[T]);
-    if (!(hT > 0.0)) return z_top;
+    if (growth_gap_sign(ks, ns, cn, cN, G[0], X[0]) == 1) return a;
+    if (growth_gap_sign(ks, ns, cn, cN, G[T], X[T]) != 1) return z_top;
     long long lo = 0, hi = T;
-    double hlo = h0, hhi = hT;
     while (hi - lo > 1) {
         const long long mid = lo + (hi - lo) / 2;
-        const double hm = growth_gap(ks, ns, cn, cN, G[mid], X[mid]);
-        if (hm <= 0.0) {
+        if (growth_gap_sign(ks, ns, cn, cN, G[mid], X[mid]) == 0) {
             lo = mid;
-            hlo = hm;
         } else {
             hi = mid;
-            hhi = hm;
         }
     }
+    // the gaps at the bracket, as the interpolation needs their values
+    const double hlo = growth_gap(ks, ns, cn, cN, G[lo], X[lo]);
+    const double hhi = growth_gap(ks, ns, cn, cN, G[hi], X[hi]);
     const double zl = a + (double)lo * h;
     const double zh = a + (double)hi * h;
     const double t = -hlo / (hhi - hlo);
