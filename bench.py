@@ -149,15 +149,16 @@ def copy_calibration(mib: int) -> None:
     log(f"[bench] copy calibration: {mib} MiB read + {mib} MiB written per launch, 3 launches")
 
 
-def cpu_baseline(sample_n: int, min_seconds: float) -> dict:
+def cpu_baseline(sample_n: int, min_seconds: float, cfg=None) -> dict:
     import numpy as np
 
     import inputs
     import oracle
 
     oracle.lib()
-    cfg = inputs.BoxConfig("cpu", sample_n, 1.953125 * sample_n, max(1000, int(80e6 * (sample_n / 1024) ** 3)),
-                           1e10, 1e12, index=7)
+    if cfg is None:
+        cfg = inputs.BoxConfig("cpu", sample_n, 1.953125 * sample_n, max(1000, int(80e6 * (sample_n / 1024) ** 3)),
+                               1e10, 1e12, index=7)
     w, S = inputs.make_box(cfg)
     S64 = S.numpy().astype(np.float64)
     wn = w.numpy()
@@ -428,6 +429,26 @@ def bench_serving(args) -> dict:
     offered = sum(r.n ** 3 for r in reqs) / args.serve_seconds
     log(f"[bench] serving {len(reqs)} requests ({offered / 1e9:.2f} G cells/s offered)")
     st = server.serve(reqs)
+    # the same requests one at a time on one stream (no batching, no overlap), device time only
+    outs = {n: (torch.empty((n, n, n), dtype=torch.float32, device=dev),
+                torch.empty((n, n, n), dtype=torch.float32, device=dev)) for n in boxes}
+    serial_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs:
+        b = boxes[r.n]
+        J, z = outs[r.n]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.plan.radiation(b.S, [r.l_mfp], out=[J])
+        b.plan.zre(J, b.w, [server.history(r.history)], out=[z])
+        e1.record()
+        serial_ms.append((e0, e1))
+    torch.cuda.synchronize()
+    serial_el = time.perf_counter() - t0
+    serial_lat = sorted(a.elapsed_time(b_) for a, b_ in serial_ms)
+    del outs
+    log(f"[bench] serial: {len(reqs)} requests in {serial_el:.2f} s")
     return _common(args, "served grid cells/s (Poisson requests, p50/p99 latency)", st["cells_per_s_busy"],
                    1e3 * st["busy_s"] / max(1, st["batches"]), WORKLOADS["c5"]["desc"],
                    {"p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
@@ -436,6 +457,9 @@ def bench_serving(args) -> dict:
                     "makespan_s": round(st["makespan_s"], 3), "busy_s": round(st["busy_s"], 3),
                     "slots": st["slots"], "max_batches_in_flight": st["max_batches_in_flight"],
                     "hbm_budget_gb": args.hbm_budget_gb, "arrivals_s": args.serve_seconds,
+                    "serial_single_calls": {"value": st["cells"] / serial_el, "seconds": round(serial_el, 3),
+                                            "p50_ms": round(_pct(serial_lat, 50), 3),
+                                            "p99_ms": round(_pct(serial_lat, 99), 3)},
                     "fft_schedule": scheds})
 
 
@@ -455,6 +479,8 @@ def main() -> int:
     ap.add_argument("--tune-reps", type=int, default=5, help="timed radiation passes per schedule pair and round")
     ap.add_argument("--tune-cache", default=None, metavar="JSON",
                     help="schedule cache keyed by device and grid size (default: tune in this process)")
+    ap.add_argument("--cpu-only", default=None, metavar="N[,N...]",
+                    help="time only the CPU oracle on boxes of these sizes (64 is the c1 box) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain copy of MIB MiB (for HBM counter calibration)")
     args = ap.parse_args()
@@ -463,6 +489,13 @@ def main() -> int:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
         return 2
+
+    if args.cpu_only:
+        import inputs
+        for n in [int(x) for x in args.cpu_only.split(",")]:
+            res = cpu_baseline(n, args.cpu_seconds, inputs.CONFIGS["c1"] if n == 64 else None)
+            print(json.dumps({"cpu_only": True, "n": n, "cpu_baseline": res}), flush=True)
+        return 0
 
     import torch
 
