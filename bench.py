@@ -69,9 +69,9 @@ def algorithmic_bytes(n: int) -> dict:
         "fft_z_c2r": half + 4 * n3,
         "rank_hist": 4 * n3,
         "rank_pass0": 8 * n3 + 12 * n3,      # J, w in; key, index, w out
-        "rank_pass1": 12 * n3 + 12 * n3,
-        "rank_pass2": 12 * n3 + 12 * n3,
-        "rank_pass3": 12 * n3 + 8 * n3,      # index, w out
+        "rank_pass1": 12 * n3 + 10 * n3,     # key's top 16 bits out
+        "rank_pass2": 10 * n3 + 9 * n3,      # key's top 8 bits out
+        "rank_pass3": 9 * n3 + 8 * n3,       # index, w out
         "match_tile_sums": 4 * n3,                 # sorted weights in
         "match_scan_partition": 8 * n3 + 8 * n3,   # rank order, w in; (cell, z) pairs out
         "match_partition2": 8 * n3 + 8 * n3,       # (cell, z) pairs in and out

@@ -1,6 +1,8 @@
-// Rank order for abundance matching on gfx950 (Sec. 3.4.2: "ranked in
-// descending order"): a stable least-significant-digit radix sort of
+// Rank order for abundance matching on gfx950 (Sec. 3.4.2: cells ordered by
+// intensity, highest first): a stable least-significant-digit radix sort of
 // (key, cell index[, weight]) with 8-bit digits, one streaming pass per digit.
+// A pass writes only the key bits later passes still read: all 32 after the
+// first digit, the top 16 after the second, the top 8 after the third.
 //
 // Keys: FP32 intensity -> uint32 whose ascending order is the descending order
 // of the intensity (-0 folded onto +0).  The input is read in cell-index order
@@ -180,10 +182,10 @@ __global__ __launch_bounds__(1024) void k_qmin(const int* __restrict__ qtile, lo
 // come from J and the index is the position.  LAST: only the values (and
 // weights) are written.  CARRY: weights travel with the keys; pass 0 also
 // checks them and stores the smallest ulp exponent of each tile in qtile[tile].
-template <int kThreads, bool FIRST, bool LAST, bool CARRY>
+template <int kThreads, bool FIRST, bool LAST, bool CARRY, int KIN = 4, int KOUT = 4>
 __global__ __launch_bounds__(kThreads) void k_onesweep(
-    const float* __restrict__ J, const unsigned* __restrict__ keys_in, const unsigned* __restrict__ vals_in,
-    const float* __restrict__ w_in, unsigned* __restrict__ keys_out, unsigned* __restrict__ vals_out,
+    const float* __restrict__ J, const void* __restrict__ keys_in_v, const unsigned* __restrict__ vals_in,
+    const float* __restrict__ w_in, void* __restrict__ keys_out_v, unsigned* __restrict__ vals_out,
     float* __restrict__ w_out, unsigned* __restrict__ lb, unsigned* __restrict__ lb_next,
     unsigned* __restrict__ lb_next2, int* __restrict__ qtile, Ctrl* ctrl, int pass, long long n) {
     constexpr int kWaves = kThreads / 64;
@@ -198,6 +200,18 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     __shared__ int s_qmin[kWaves];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // keys travel with only the digits later passes still need: KIN / KOUT
+    // bytes, the top bytes of the 32-bit key
+    auto load_key = [&](unsigned i) -> unsigned {
+        if (KIN == 4) return reinterpret_cast<const unsigned*>(keys_in_v)[i];
+        if (KIN == 2) return (unsigned)reinterpret_cast<const unsigned short*>(keys_in_v)[i] << 16;
+        return (unsigned)reinterpret_cast<const unsigned char*>(keys_in_v)[i] << 24;
+    };
+    auto store_key = [&](unsigned i, unsigned k) {
+        if (KOUT == 4) reinterpret_cast<unsigned*>(keys_out_v)[i] = k;
+        else if (KOUT == 2) reinterpret_cast<unsigned short*>(keys_out_v)[i] = (unsigned short)(k >> 16);
+        else reinterpret_cast<unsigned char*>(keys_out_v)[i] = (unsigned char)(k >> 24);
+    };
     if (tid == 0) s_tile = atomicAdd(&ctrl->tickets[pass], 1u);
     for (int i = tid; i < kWaves * 256; i += kThreads) (&wcnt[0][0])[i] = 0;
     __syncthreads();
@@ -229,7 +243,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
                 key[j] = __float_as_uint(J[pos]);
                 val[j] = pos;
             } else {
-                key[j] = keys_in[pos];
+                key[j] = load_key(pos);
                 val[j] = vals_in[pos];
             }
             if (CARRY) wt[j] = w_in[pos];
@@ -244,7 +258,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
                 key[j] = __float_as_uint(J[pc]);
                 val[j] = pos;
             } else {
-                key[j] = keys_in[pc];
+                key[j] = load_key(pc);
                 val[j] = vals_in[pc];
             }
             if (CARRY) wt[j] = w_in[pc];
@@ -369,7 +383,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
             const unsigned t = gbase[dd] + ((unsigned)i - loff[dd]);  // i >= loff[dd] inside the digit's run
             if (t < (unsigned)n) {
                 dst[k] = t;
-                if (!LAST) keys_out[t] = kk;
+                if (!LAST) store_key(t, kk);
             }
         }
     }
@@ -418,21 +432,21 @@ static void launch_passes(const amber_plan_s* p, const float* d_J, const float* 
         AMBER_LAUNCH(p, "rank_pass0", (k_onesweep<T, true, false, true>), grid, blk, s, d_J, nullptr, nullptr, d_w,
                      keys[1], vals[1], wts[1], lb[0], lb[1], nullptr, qtile, ctrl, 0, n);
         AMBER_LAUNCH(p, "rank_qmin", k_qmin, dim3(1), dim3(1024), s, qtile, n_tiles, ctrl);
-        AMBER_LAUNCH(p, "rank_pass1", (k_onesweep<T, false, false, true>), grid, blk, s, nullptr, keys[1], vals[1],
-                     wts[1], keys[0], vals[0], wts[0], lb[1], lb[0], nullptr, nullptr, ctrl, 1, n);
-        AMBER_LAUNCH(p, "rank_pass2", (k_onesweep<T, false, false, true>), grid, blk, s, nullptr, keys[0], vals[0],
-                     wts[0], keys[1], vals[1], wts[1], lb[0], lb[1], nullptr, nullptr, ctrl, 2, n);
-        AMBER_LAUNCH(p, "rank_pass3", (k_onesweep<T, false, true, true>), grid, blk, s, nullptr, keys[1], vals[1],
-                     wts[1], nullptr, final_vals, wts[0], lb[1], lb[0], lb[2], nullptr, ctrl, 3, n);
+        AMBER_LAUNCH(p, "rank_pass1", (k_onesweep<T, false, false, true, 4, 2>), grid, blk, s, nullptr, keys[1],
+                     vals[1], wts[1], keys[0], vals[0], wts[0], lb[1], lb[0], nullptr, nullptr, ctrl, 1, n);
+        AMBER_LAUNCH(p, "rank_pass2", (k_onesweep<T, false, false, true, 2, 1>), grid, blk, s, nullptr, keys[0],
+                     vals[0], wts[0], keys[1], vals[1], wts[1], lb[0], lb[1], nullptr, nullptr, ctrl, 2, n);
+        AMBER_LAUNCH(p, "rank_pass3", (k_onesweep<T, false, true, true, 1, 4>), grid, blk, s, nullptr, keys[1],
+                     vals[1], wts[1], nullptr, final_vals, wts[0], lb[1], lb[0], lb[2], nullptr, ctrl, 3, n);
     } else {
         AMBER_LAUNCH(p, "rank_pass0", (k_onesweep<T, true, false, false>), grid, blk, s, d_J, nullptr, nullptr,
                      nullptr, keys[1], vals[1], nullptr, lb[0], lb[1], nullptr, nullptr, ctrl, 0, n);
-        AMBER_LAUNCH(p, "rank_pass1", (k_onesweep<T, false, false, false>), grid, blk, s, nullptr, keys[1], vals[1],
-                     nullptr, keys[0], vals[0], nullptr, lb[1], lb[0], nullptr, nullptr, ctrl, 1, n);
-        AMBER_LAUNCH(p, "rank_pass2", (k_onesweep<T, false, false, false>), grid, blk, s, nullptr, keys[0], vals[0],
-                     nullptr, keys[1], vals[1], nullptr, lb[0], lb[1], nullptr, nullptr, ctrl, 2, n);
-        AMBER_LAUNCH(p, "rank_pass3", (k_onesweep<T, false, true, false>), grid, blk, s, nullptr, keys[1], vals[1],
-                     nullptr, nullptr, final_vals, nullptr, lb[1], lb[0], lb[2], nullptr, ctrl, 3, n);
+        AMBER_LAUNCH(p, "rank_pass1", (k_onesweep<T, false, false, false, 4, 2>), grid, blk, s, nullptr, keys[1],
+                     vals[1], nullptr, keys[0], vals[0], nullptr, lb[1], lb[0], nullptr, nullptr, ctrl, 1, n);
+        AMBER_LAUNCH(p, "rank_pass2", (k_onesweep<T, false, false, false, 2, 1>), grid, blk, s, nullptr, keys[0],
+                     vals[0], nullptr, keys[1], vals[1], nullptr, lb[0], lb[1], nullptr, nullptr, ctrl, 2, n);
+        AMBER_LAUNCH(p, "rank_pass3", (k_onesweep<T, false, true, false, 1, 4>), grid, blk, s, nullptr, keys[1],
+                     vals[1], nullptr, nullptr, final_vals, nullptr, lb[1], lb[0], lb[2], nullptr, ctrl, 3, n);
     }
 }
 
