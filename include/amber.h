@@ -167,7 +167,8 @@ int amber_plan_get_schedule(amber_plan plan, int* col, int* z);
  * under every (column, z) candidate pair, `reps` passes per pair after one
  * untimed pass, in three rounds (a pair's figure is its fastest round), and
  * sets the plan to the fastest pair.  The default pair is kept unless another
- * is faster by more than 2 %.  d_src: N^3 FP32 (read only); d_J: N^3 FP32
+ * is faster by more than 2 %; among those, the lowest-index pair within 1 % of
+ * the fastest is taken.  d_src: N^3 FP32 (read only); d_J: N^3 FP32
  * scratch, overwritten; d_ws: amber_workspace_bytes(plan, 1) bytes.
  * ms_out: host array of n_col * n_z floats (row-major [col][z], mean ms per
  * pass), may be NULL; col, z: the chosen pair, may be NULL.  Creates and

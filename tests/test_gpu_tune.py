@@ -131,8 +131,16 @@ def test_tuner_picks_a_pair_and_keeps_parity(amber):
     assert plan.schedule == (res["col"], res["z"])
     ms = np.array(res["ms"])
     assert ms.shape == (len(cand["col"]), len(cand["z"])) and np.all(np.isfinite(ms)) and np.all(ms > 0)
-    # the chosen pair is the default or beats it by the stated margin
-    assert (res["col"], res["z"]) == (0, 0) or ms[res["col"], res["z"]] < 0.98 * ms[0, 0]
+    # the chosen pair is the default, or beats it by the stated margin and is
+    # the first pair within 1 % of the fastest
+    c, z = res["col"], res["z"]
+    if (c, z) != (0, 0):
+        flat = ms.astype(np.float32).reshape(-1)      # the library compares in FP32
+        beats = np.float32(0.98) * flat[0]
+        near = np.float32(1.01) * flat.min()
+        k = c * ms.shape[1] + z
+        assert flat[k] < beats and flat[k] <= near
+        assert not any(flat[j] < beats and flat[j] <= near for j in range(1, k))
     print(f"tuned n={n}: {res}", flush=True)
     (J,) = plan.radiation(torch.from_numpy(S).cuda(), [l])
     J_ref = oracle.radiation(S.astype(np.float64), L, l)
