@@ -74,8 +74,8 @@ def algorithmic_bytes(n: int) -> dict:
         "rank_pass3": 9 * n3 + 8 * n3,       # index, w out
         "match_tile_sums": 4 * n3,                 # sorted weights in
         "match_scan_partition": 8 * n3 + 8 * n3,   # rank order, w in; (cell, z) pairs out
-        "match_partition2": 8 * n3 + 8 * n3,       # (cell, z) pairs in and out
-        "match_leaf_scatter": 8 * n3 + 4 * n3,     # (cell, z) pairs in; z_re out
+        "match_partition2": 8 * n3 + 6 * n3,       # (cell, z) pairs in; (16-bit offset, z) out
+        "match_leaf_scatter": 6 * n3 + 4 * n3,     # (offset, z) pairs in; z_re out
     }
 
 

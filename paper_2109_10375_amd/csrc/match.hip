@@ -673,12 +673,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
 // b (positions [b S1, (b+1) S1), cells of the same range) are split into kL2
 // sub-buckets of S2 = S1 / kL2 cells.  Tiles never straddle buckets; each tile
 // takes its slots in a sub-bucket with one atomic add on that sub-bucket's
-// fill counter (order inside a sub-bucket does not matter).
+// fill counter (order inside a sub-bucket does not matter).  A pair leaves
+// with its cell's 16-bit offset inside the sub-bucket (S2 <= 16384): the
+// sub-buckets tile the positions exactly as their cells tile the grid, so
+// the position gives back the rest of the cell index.
 __global__ __launch_bounds__(kPartThreads) void k_partition2(const unsigned* __restrict__ in_idx,
                                                          const float* __restrict__ in_z, long long n,
                                                          unsigned* __restrict__ fill, unsigned S1, unsigned S2,
                                                          double s2_rinv, unsigned tiles_per_bucket,
-                                                         unsigned* __restrict__ out_idx,
+                                                         unsigned short* __restrict__ out_off,
                                                          float* __restrict__ out_z) {
     __shared__ unsigned lcnt[kL2];
     __shared__ unsigned loff[kL2];
@@ -748,7 +751,7 @@ __global__ __launch_bounds__(kPartThreads) void k_partition2(const unsigned* __r
                 const unsigned t = gbase[s2] + ((unsigned)i - loff[s2]);
                 if (t < (unsigned)n) {
                     dst[kk] = t;
-                    out_idx[t] = c;
+                    out_off[t] = (unsigned short)(rel - s2 * S2);  // < S2 <= 16384
                 }
             }
         }
@@ -766,12 +769,16 @@ __global__ __launch_bounds__(kPartThreads) void k_partition2(const unsigned* __r
 // Last level: block L owns cells [L S, (L+1) S) (S <= 16384, a whole number of
 // the previous level's ranges, whose pairs sit at exactly the positions of
 // their cells) and the pairs at positions [L S, (L+1) S); it places z by cell
-// in LDS and writes the run of z_re contiguously.
+// in LDS and writes the run of z_re contiguously.  OFF16: the pairs carry
+// their cell's offset inside its range of R cells (the second level's
+// sub-buckets), so pair i of the block belongs to cell floor(i/R) R + offset;
+// otherwise they carry the cell index.
 constexpr int kLeafMax = 16384;
 constexpr int kLeafThreads = 1024;
-__global__ __launch_bounds__(kLeafThreads) void k_leaf_scatter(const unsigned* __restrict__ in_idx,
+template <bool OFF16>
+__global__ __launch_bounds__(kLeafThreads) void k_leaf_scatter(const void* __restrict__ in_cell,
                                                                const float* __restrict__ in_z, long long n, unsigned S,
-                                                               float* __restrict__ out) {
+                                                               unsigned R, double r_rinv, float* __restrict__ out) {
     constexpr int kR = kLeafMax / kLeafThreads;
     __shared__ float zl[kLeafMax];
     const long long start = (long long)blockIdx.x * S;
@@ -784,13 +791,22 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_scatter(const unsigned* _
     for (int r = 0; r < kR; ++r) {
         const unsigned i = threadIdx.x + r * kLeafThreads;
         const long long at = start + (i < valid ? i : 0u);
-        c[r] = in_idx[at];
+        if (OFF16) {
+            c[r] = reinterpret_cast<const unsigned short*>(in_cell)[at];
+        } else {
+            c[r] = reinterpret_cast<const unsigned*>(in_cell)[at];
+        }
         z[r] = in_z[at];
     }
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const unsigned i = threadIdx.x + r * kLeafThreads;
-        const long long rel = (long long)c[r] - start;
+        long long rel;
+        if (OFF16) {
+            rel = (long long)div_exact(i, R, r_rinv) * R + c[r];
+        } else {
+            rel = (long long)c[r] - start;
+        }
         if (i < valid && rel >= 0 && rel < (long long)valid) zl[rel] = z[r];
     }
     __syncthreads();
@@ -832,7 +848,7 @@ int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, flo
     float* p1_z[kGroup] = {reinterpret_cast<float*>(ws + L.keys[1]), reinterpret_cast<float*>(ws + L.vals[1]),
                            reinterpret_cast<float*>(ws + L.wts[1])};
     // second level: its own buffers, so the rank order survives for later groups
-    unsigned* p2_idx = reinterpret_cast<unsigned*>(ws + L.part2[0]);
+    unsigned short* p2_off = reinterpret_cast<unsigned short*>(ws + L.part2[0]);
     float* p2_z = reinterpret_cast<float*>(ws + L.part2[1]);
     const unsigned S1 = (unsigned)(n / kL1);  // n is a multiple of 512
     const bool two_level = S1 > (unsigned)kLeafMax;
@@ -877,13 +893,13 @@ int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, flo
         for (int i = 0; i < hs.n; ++i) {
             if (two_level) {
                 AMBER_LAUNCH(p, "match_clear", k_clear, dim3(256), dim3(256), s, fill2, 65536);
-                AMBER_LAUNCH(p, "match_partition2", k_partition2, dim3(kL1 * tpb), dim3(kPartThreads), s, p1_idx, p1_z[i], n, fill2,
-                             S1, S2, s2_rinv, tpb, p2_idx, p2_z);
-                AMBER_LAUNCH(p, "match_leaf_scatter", k_leaf_scatter, dim3(leaf_blocks), dim3(kLeafThreads), s,
-                             p2_idx, p2_z, n, leaf, d_zre[h0 + i]);
+                AMBER_LAUNCH(p, "match_partition2", k_partition2, dim3(kL1 * tpb), dim3(kPartThreads), s, p1_idx,
+                             p1_z[i], n, fill2, S1, S2, s2_rinv, tpb, p2_off, p2_z);
+                AMBER_LAUNCH(p, "match_leaf_scatter", k_leaf_scatter<true>, dim3(leaf_blocks), dim3(kLeafThreads), s,
+                             p2_off, p2_z, n, leaf, S2, s2_rinv, d_zre[h0 + i]);
             } else {
-                AMBER_LAUNCH(p, "match_leaf_scatter", k_leaf_scatter, dim3(leaf_blocks), dim3(kLeafThreads), s,
-                             p1_idx, p1_z[i], n, leaf, d_zre[h0 + i]);
+                AMBER_LAUNCH(p, "match_leaf_scatter", k_leaf_scatter<false>, dim3(leaf_blocks), dim3(kLeafThreads), s,
+                             p1_idx, p1_z[i], n, leaf, S2, s2_rinv, d_zre[h0 + i]);
             }
         }
     }
