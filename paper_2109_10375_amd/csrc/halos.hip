@@ -534,31 +534,25 @@ __global__ __launch_bounds__(256) void k_axis_table(double4* __restrict__ tab, i
     tab[m] = (2 * s == n) ? make_double4(w, 1.0, 0.0, 1.0) : make_double4(w, cos(a), sin(a), 0.0);
 }
 
-// One block per row (x, y) of the main half spectrum (threads over kz < n/2),
-// then one block per x of the Nyquist plane (threads over y, kz = n/2).
+// kCombineRows rows (x, y) of the main half spectrum per block (threads over
+// kz < n/2), then one block per x of the Nyquist plane (threads over y,
+// kz = n/2).
 //   S = [A + phi B] / (2 W),  phi = e^{i alpha} cos(n_nyq pi / 2),
 // W and e^{i alpha} being products of the per-axis factors.
+constexpr unsigned kCombineRows = 8;
 __global__ __launch_bounds__(256) void k_combine(float2* __restrict__ spec_a, float2* __restrict__ nyq_a,
                                                  const float2* __restrict__ spec_b, const float2* __restrict__ nyq_b,
                                                  const double4* __restrict__ tab, int n, int interlace) {
     const int h = n / 2;
     const unsigned b = blockIdx.x;
-    const unsigned rows = (unsigned)n * (unsigned)n;
-    const bool nyq_plane = b >= rows;
-    const int x = nyq_plane ? (int)(b - rows) : (int)(b / (unsigned)n);
-    const int y_row = nyq_plane ? 0 : (int)(b % (unsigned)n);
-    const double4 tx = tab[x];
-    const int cnt = nyq_plane ? n : h;
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-        const int y = nyq_plane ? i : y_row, kz = nyq_plane ? h : i;
-        const double4 ty = tab[y], tz = tab[kz];
-        const size_t off = nyq_plane ? (size_t)x * n + i : (size_t)b * h + i;
-        float2* a = (nyq_plane ? nyq_a : spec_a) + off;
+    const unsigned main_blocks = (unsigned)n * (unsigned)n / kCombineRows;
+    const bool nyq_plane = b >= main_blocks;
+    auto mode = [&](float2* a, const float2* bp, const double4& tx, const double4& ty, const double4& tz) {
         const float2 av = *a;
         double re = av.x, im = av.y;
         const double W = tx.x * ty.x * tz.x;
         if (interlace) {
-            const float2 bv = (nyq_plane ? nyq_b : spec_b)[off];
+            const float2 bv = *bp;
             // e^{i alpha} over the non-Nyquist axes (the Nyquist entries are 1)
             const double c1 = tx.y * ty.y - tx.z * ty.z, s1 = tx.y * ty.z + tx.z * ty.y;
             double c = c1 * tz.y - s1 * tz.z, sn = c1 * tz.z + s1 * tz.y;
@@ -570,6 +564,23 @@ __global__ __launch_bounds__(256) void k_combine(float2* __restrict__ spec_a, fl
             im = 0.5 * (im + c * bv.y + sn * bv.x);
         }
         *a = make_float2((float)(re / W), (float)(im / W));
+    };
+    if (!nyq_plane) {
+        for (unsigned r = 0; r < kCombineRows; ++r) {
+            const unsigned row = b * kCombineRows + r;
+            const double4 tx = tab[row / (unsigned)n], ty = tab[row % (unsigned)n];
+            for (int i = threadIdx.x; i < h; i += blockDim.x) {
+                const size_t off = (size_t)row * h + i;
+                mode(spec_a + off, spec_b + off, tx, ty, tab[i]);
+            }
+        }
+    } else {
+        const int x = (int)(b - main_blocks);
+        const double4 tx = tab[x], tz = tab[h];
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const size_t off = (size_t)x * n + i;
+            mode(nyq_a + off, nyq_b + off, tx, tab[i], tz);
+        }
     }
 }
 
@@ -662,8 +673,8 @@ int halo_source_spectrum(const amber_plan_s* p, const float* d_pos, const float*
     if (rc != AMBER_OK) return rc;
     double4* tab = reinterpret_cast<double4*>(ws + L.halo_tab);
     AMBER_LAUNCH(p, "halo_axis_table", k_axis_table, dim3((unsigned)((n + 255) / 256)), dim3(256), s, tab, n, scheme);
-    AMBER_LAUNCH(p, "halo_combine", k_combine, dim3((unsigned)((long long)n * n + n)), dim3(256), s, sa, na, sb, nb,
-                 tab, n, interlace);
+    AMBER_LAUNCH(p, "halo_combine", k_combine, dim3((unsigned)((long long)n * n / kCombineRows + n)), dim3(256), s, sa,
+                 na, sb, nb, tab, n, interlace);
     AMBER_HIP_CHECK(hipGetLastError());
     return AMBER_OK;
 }
