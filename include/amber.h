@@ -76,9 +76,11 @@ typedef struct {
  * d_table must point to T + 1 doubles on the device holding exactly the values
  * written by amber_weibull_table() for this struct.
  * d_growth selects the matching equation (Sec. 3.4.2): NULL weights every cell
- * by its gas mass 1 + delta at z_mid; otherwise it points to T + 1 device
- * doubles G_j = D(z_j)/D(z_mid) (amber_growth_table) and the overdensities are
- * extrapolated linearly to each redshift, delta(z) = G delta. */
+ * by its gas mass 1 + delta at z_mid; otherwise it points to T + 1 pairs
+ * (X_j, G_j) of device doubles (2 (T + 1) doubles, 16-byte aligned, as written
+ * by amber_growth_table), G_j = D(z_j)/D(z_mid), and the overdensities are
+ * extrapolated linearly to each redshift, delta(z) = G delta.  The pairs keep
+ * a node's two values in one 16-byte read for the bisection. */
 typedef struct {
     double a_w, b_w, c_w;
     double h, z_top;
@@ -110,7 +112,9 @@ int amber_weibull_table(const amber_weibull* w, double* host_table, int64_t n_en
  * j = 0..T, for a flat universe of matter density omega_m (0 < omega_m <= 1)
  * and a cosmological constant; D is the growing mode, D = a while matter
  * dominates: D(a) = a 2F1(1/3, 1; 11/6; -(1 - omega_m)/omega_m a^3) (the paper's
- * cosmology, Sec. 2, has omega_m = 0.3).  n_entries must equal w->table_n. */
+ * cosmology, Sec. 2, has omega_m = 0.3).  Written as pairs: host_table[2j] =
+ * X_j (the value amber_weibull_table writes) and host_table[2j + 1] = G_j, so
+ * host_table holds 2 n_entries doubles; n_entries must equal w->table_n. */
 int amber_growth_table(const amber_weibull* w, double z_mid, double omega_m, double* host_table,
                        int64_t n_entries);
 

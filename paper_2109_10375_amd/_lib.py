@@ -168,12 +168,12 @@ class History:
 
     def with_growth(self, z_mid: float, omega_m: float = 0.3) -> "History":
         """The same history matched with growth-rescaled overdensities
-        (amber_growth_table: G_j = D(z_j)/D(z_mid) on the device)."""
+        (amber_growth_table: pairs (X_j, G_j = D(z_j)/D(z_mid)) on the device)."""
         w = AmberWeibull.from_buffer_copy(self.w)
         h = History.__new__(History)
         h.w = w
         h.table = self.table
-        host = torch.empty(w.table_n, dtype=torch.float64)
+        host = torch.empty(2 * w.table_n, dtype=torch.float64)
         _check(lib().amber_growth_table(ctypes.byref(w), float(z_mid), float(omega_m),
                                         ctypes.c_void_p(host.data_ptr()), w.table_n), "amber_growth_table")
         h.growth = host.to(self.table.device)
@@ -183,8 +183,9 @@ class History:
 
     @staticmethod
     def growth_table_host(w: AmberWeibull, z_mid: float, omega_m: float = 0.3) -> torch.Tensor:
-        """The library's host growth table for a fitted history (no GPU work)."""
-        host = torch.empty(w.table_n, dtype=torch.float64)
+        """The library's host growth table for a fitted history (no GPU work):
+        pairs (X_j, G_j), 2 table_n doubles."""
+        host = torch.empty(2 * w.table_n, dtype=torch.float64)
         _check(lib().amber_growth_table(ctypes.byref(w), float(z_mid), float(omega_m),
                                         ctypes.c_void_p(host.data_ptr()), w.table_n), "amber_growth_table")
         return host

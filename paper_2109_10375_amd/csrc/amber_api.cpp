@@ -183,13 +183,15 @@ int amber_weibull_fit(const amber_history* hist, amber_weibull* out) {
     return amber_weibull_from_coeffs(a, b, c, out);
 }
 
+// X_j = x_i(z_j), z_j = a_w + j h (Sec. 3.1.2, Eq. weibull).
+static double weibull_node(const amber_weibull* w, int64_t j) {
+    const double a = w->a_w, z = a + (double)j * w->h;
+    return std::exp(-std::pow((z - a) / w->b_w, w->c_w));
+}
+
 int amber_weibull_table(const amber_weibull* w, double* host_table, int64_t n_entries) {
     if (!w || !host_table || n_entries != w->table_n || n_entries < 2) return AMBER_E_ARG;
-    const double a = w->a_w, b = w->b_w, c = w->c_w, h = w->h;
-    for (int64_t j = 0; j < n_entries; ++j) {
-        const double z = a + (double)j * h;
-        host_table[j] = std::exp(-std::pow((z - a) / b, c));
-    }
+    for (int64_t j = 0; j < n_entries; ++j) host_table[j] = weibull_node(w, j);
     return AMBER_OK;
 }
 
@@ -217,7 +219,10 @@ int amber_growth_table(const amber_weibull* w, double z_mid, double omega_m, dou
     if (!w || !host_table || n_entries != w->table_n || n_entries < 2) return AMBER_E_ARG;
     if (!(omega_m > 0.0) || !(omega_m <= 1.0) || !std::isfinite(z_mid) || !(z_mid > -1.0)) return AMBER_E_ARG;
     const double dmid = growth_factor(z_mid, omega_m);
-    for (int64_t j = 0; j < n_entries; ++j) host_table[j] = growth_factor(w->a_w + (double)j * w->h, omega_m) / dmid;
+    for (int64_t j = 0; j < n_entries; ++j) {
+        host_table[2 * j] = weibull_node(w, j);
+        host_table[2 * j + 1] = growth_factor(w->a_w + (double)j * w->h, omega_m) / dmid;
+    }
     return AMBER_OK;
 }
 
@@ -499,6 +504,7 @@ int amber_zre(amber_plan plan, const float* d_J, const float* d_w, const amber_w
     for (int i = 0; i < n_hist; ++i) {
         const amber_weibull& w = hist[i];
         if (!d_zre[i] || !w.d_table || w.table_n < 2) return AMBER_E_ARG;
+        if (reinterpret_cast<uintptr_t>(w.d_growth) % 16 != 0) return AMBER_E_ARG;
         if (!(w.a_w > 0.0) || !(w.b_w > 0.0) || !(w.c_w > 0.0) || !(w.h > 0.0) || !(w.z_top > w.a_w) ||
             !std::isfinite(w.z_top))
             return AMBER_E_HISTORY;
@@ -527,6 +533,7 @@ static int check_item(const amber_batch_item& it) {
     for (int h = 0; h < it.n_hist; ++h) {
         const amber_weibull& w = it.hist[h];
         if (!w.d_table || w.table_n < 2) return AMBER_E_ARG;
+        if (reinterpret_cast<uintptr_t>(w.d_growth) % 16 != 0) return AMBER_E_ARG;
         if (!(w.a_w > 0.0) || !(w.b_w > 0.0) || !(w.c_w > 0.0) || !(w.h > 0.0) || !(w.z_top > w.a_w) ||
             !std::isfinite(w.z_top))
             return AMBER_E_HISTORY;

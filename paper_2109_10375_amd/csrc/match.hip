@@ -96,7 +96,7 @@ struct HistArg {
     double a, b, inv_c, h, z_top;
     long long T;
     const double* X;
-    const double* G;  // growth ratios D(z_j)/D(z_mid) at the nodes, or null
+    const double2* XG;  // (X_j, D(z_j)/D(z_mid)) at the nodes, or null
     float* out;
 };
 
@@ -190,22 +190,25 @@ __device__ __forceinline__ int growth_gap_sign(double ks, double ns, double cn, 
 }
 
 __device__ double invert_growth(double ks, double ns, double cn, double cN, double a, double h, long long T,
-                                double z_top, const double* __restrict__ X, const double* __restrict__ G) {
+                                double z_top, const double2* __restrict__ XG) {
 #pragma clang fp contract(off)
-    if (growth_gap_sign(ks, ns, cn, cN, G[0], X[0]) == 1) return a;
-    if (growth_gap_sign(ks, ns, cn, cN, G[T], X[T]) != 1) return z_top;
+    const double2 n0 = XG[0], nT = XG[T];
+    if (growth_gap_sign(ks, ns, cn, cN, n0.y, n0.x) == 1) return a;
+    if (growth_gap_sign(ks, ns, cn, cN, nT.y, nT.x) != 1) return z_top;
     long long lo = 0, hi = T;
     while (hi - lo > 1) {
         const long long mid = lo + (hi - lo) / 2;
-        if (growth_gap_sign(ks, ns, cn, cN, G[mid], X[mid]) == 0) {
+        const double2 nm = XG[mid];  // X and G of the node in one read
+        if (growth_gap_sign(ks, ns, cn, cN, nm.y, nm.x) == 0) {
             lo = mid;
         } else {
             hi = mid;
         }
     }
     // the gaps at the bracket, as the interpolation needs their values
-    const double hlo = growth_gap(ks, ns, cn, cN, G[lo], X[lo]);
-    const double hhi = growth_gap(ks, ns, cn, cN, G[hi], X[hi]);
+    const double2 nl = XG[lo], nh = XG[hi];
+    const double hlo = growth_gap(ks, ns, cn, cN, nl.y, nl.x);
+    const double hhi = growth_gap(ks, ns, cn, cN, nh.y, nh.x);
     const double zl = a + (double)lo * h;
     const double zh = a + (double)hi * h;
     const double t = -hlo / (hhi - hlo);
@@ -551,12 +554,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
     auto z_of = [&](const HistArg& H, long long gl, const double* x, float* zf) {
 #pragma clang fp contract(off)
         if constexpr (GROWTH) {
-            if (H.G) {
+            if (H.XG) {
 #pragma unroll
                 for (int j = 0; j < kPer; ++j) {
                     const double ks = (double)(p0 + j + 1) * unit;
                     zf[j] = pos[j] != 0xffffffffu
-                                ? (float)invert_growth(ks, ns, cn[j], tot, H.a, H.h, H.T, H.z_top, H.X, H.G)
+                                ? (float)invert_growth(ks, ns, cn[j], tot, H.a, H.h, H.T, H.z_top, H.XG)
                                 : 0.0f;
                 }
                 return;
@@ -566,7 +569,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
         // thread: a rank with X_jm >= F > X_jm+1 has exactly this bracket
         // (X is non-increasing), so only its own t needs computing.
         double xm0 = 0.0, xm1 = 0.0, zm = 0.0, denm = 0.0, dzm = 0.0;
-        if (!H.G) {
+        if (!H.XG) {
             const double fm = __ddiv_rn(cn[kPer / 2], tot);
             int km = 0;
 #pragma unroll
@@ -622,7 +625,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
     if constexpr (NH == 1) {
         long long gl0 = 0;
         double x0[8] = {};
-        if (!hs.h[0].G) window(hs.h[0], gl0, x0);
+        if (!hs.h[0].XG) window(hs.h[0], gl0, x0);
         z_of(hs.h[0], gl0, x0, zf0);
     }
 
@@ -656,7 +659,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
             long long gl = 0;
             double x[8] = {};
             float zf[kPer];
-            if (!H.G) window(H, gl, x);
+            if (!H.XG) window(H, gl, x);
             z_of(H, gl, x, zf);
 #pragma unroll
             for (int j = 0; j < kPer; ++j)
@@ -871,11 +874,11 @@ int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, flo
         for (int i = 0; i < hs.n; ++i) {
             const amber_weibull& w = hist[h0 + i];
             hs.h[i] = HistArg{w.a_w, w.b_w, 1.0 / w.c_w, w.h, w.z_top, (long long)(w.table_n - 1), w.d_table,
-                              w.d_growth, d_zre[h0 + i]};
+                              reinterpret_cast<const double2*>(w.d_growth), d_zre[h0 + i]};
         }
         if (g > 0) AMBER_LAUNCH(p, "match_clear", k_clear, dim3(1), dim3(256), s, fill1, kL1);
         bool growth = false;  // the growth inversion lives in its own kernels (it needs more registers)
-        for (int i = 0; i < hs.n; ++i) growth |= hs.h[i].G != nullptr;
+        for (int i = 0; i < hs.n; ++i) growth |= hs.h[i].XG != nullptr;
 #define AMBER_SCAN(NHV, GR)                                                                                       \
     AMBER_LAUNCH(p, "match_scan_partition", (k_scan_partition<NHV, false, GR>), grid, blk, s, perm, w_sorted, n,  \
                  ctrl, local, block_excl, fill1, sum_tpb, S1, rinv, hs, p1_idx, p1_z[0], p1_z[1], p1_z[2]);       \

@@ -124,10 +124,15 @@ def test_growth_table_identical_to_oracle(hist, z_mid):
     H = oracle.History.from_params(*hist)
     w = amber._lib.AmberWeibull()
     assert amber.lib().amber_weibull_from_coeffs(H.a, H.b, H.c, ctypes.byref(w)) == 0
-    g_lib = amber.History.growth_table_host(w, z_mid).numpy()
+    pairs = amber.History.growth_table_host(w, z_mid).numpy()
+    g_lib, x_lib = pairs[1::2], pairs[0::2]
     g_or = oracle.growth_table(H, z_mid)
     assert g_lib.shape == g_or.shape
     assert np.array_equal(g_lib.view(np.uint64), g_or.view(np.uint64))
+    # the pairs' X_j are the library's inversion table, bit for bit
+    x_tab = np.empty(w.table_n, dtype=np.float64)
+    assert amber.lib().amber_weibull_table(ctypes.byref(w), x_tab.ctypes.data_as(ctypes.c_void_p), w.table_n) == 0
+    assert np.array_equal(x_lib.view(np.uint64), x_tab.view(np.uint64))
 
 
 def test_serving_busy_time_is_the_union_of_batch_intervals():
