@@ -610,7 +610,7 @@ static int rank_any(int64_t n, const float* v32, const double* v64, uint32_t* pe
     return OR_OK;
 }
 
-/* "the data array is ranked in descending order" (Sec. 3.4.2). */
+/* The cells ordered by intensity, highest first (Sec. 3.4.2). */
 int oracle_rank_f32(int64_t n, const float* J, uint32_t* perm) { return rank_any(n, J, NULL, perm); }
 int oracle_rank_f64(int64_t n, const double* J, uint32_t* perm) { return rank_any(n, NULL, J, perm); }
 
