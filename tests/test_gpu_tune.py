@@ -170,3 +170,16 @@ def test_schedule_and_tuner_argument_errors(amber):
     S = torch.rand((64, 64, 64), device="cuda")
     with pytest.raises(amber.AmberError):
         plan.tune(S, reps=0)
+
+
+def test_tuning_launches_are_not_traced(amber):
+    """amber_plan_tune detaches an active profiler: after tuning, only the
+    launches of the calls made outside the tuner are recorded."""
+    n = 128
+    plan = amber.Plan(n, 200.0)
+    S = torch.rand((n, n, n), device="cuda")
+    plan.profile_begin(256)
+    plan.tune(S, reps=2)
+    plan.radiation(S, [3.0])
+    prof = plan.profile_end()
+    assert prof["fft_z_r2c"][0] == 1 and prof["fft_z_c2r"][0] == 1 and prof["fft_x_mul"][0] == 1
