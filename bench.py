@@ -466,7 +466,7 @@ def bench_serving(args) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="H", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
