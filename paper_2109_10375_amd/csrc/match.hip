@@ -680,12 +680,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partition(
 // with its cell's 16-bit offset inside the sub-bucket (S2 <= 16384): the
 // sub-buckets tile the positions exactly as their cells tile the grid, so
 // the position gives back the rest of the cell index.
-__global__ __launch_bounds__(kPartThreads) void k_partition2(const unsigned* __restrict__ in_idx,
-                                                         const float* __restrict__ in_z, long long n,
-                                                         unsigned* __restrict__ fill, unsigned S1, unsigned S2,
-                                                         double s2_rinv, unsigned tiles_per_bucket,
-                                                         unsigned short* __restrict__ out_off,
-                                                         float* __restrict__ out_z) {
+// The z fields of up to kGroup histories that share one ranking.
+struct ZSet {
+    const float* in[kGroup];
+    float* out[kGroup];
+};
+
+template <int NZ>
+__global__ __launch_bounds__(kPartThreads) void k_partition2(const unsigned* __restrict__ in_idx, ZSet zs,
+                                                         long long n, unsigned* __restrict__ fill, unsigned S1,
+                                                         unsigned S2, double s2_rinv, unsigned tiles_per_bucket,
+                                                         unsigned short* __restrict__ out_off) {
     __shared__ unsigned lcnt[kL2];
     __shared__ unsigned loff[kL2];
     __shared__ unsigned gbase[kL2];
@@ -702,16 +707,19 @@ __global__ __launch_bounds__(kPartThreads) void k_partition2(const unsigned* __r
     const unsigned t1 = t0 + kPartTile < bstart + S1 ? t0 + kPartTile : bstart + S1;
     const int valid = (int)(t1 - t0);
     unsigned idx[kPer], rb[kPer];
-    float z[kPer];
     // every load in flight before any is used: no branch around a load (the
     // last tile of a bucket clamps its positions instead)
     const unsigned lastv = (unsigned)valid - 1u;
+    auto at_of = [&](int j) -> unsigned {
+        const unsigned i = (unsigned)(j * kPartThreads + tid);
+        return t0 + (valid == kPartTile ? i : (i < lastv ? i : lastv));
+    };
+    float z[kPer];  // the first history's z, loaded with the cells
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
-        const unsigned i = (unsigned)(j * kPartThreads + tid);
-        const unsigned at = t0 + (valid == kPartTile ? i : (i < lastv ? i : lastv));
+        const unsigned at = at_of(j);
         idx[j] = in_idx[at];
-        z[j] = in_z[at];
+        z[j] = zs.in[0][at];
     }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
@@ -759,64 +767,78 @@ __global__ __launch_bounds__(kPartThreads) void k_partition2(const unsigned* __r
             }
         }
     }
-    __syncthreads();
+#pragma unroll 1
+    for (int h = 0; h < NZ; ++h) {
+        if (h > 0) {  // the next history's z, all loads in flight together
 #pragma unroll
-    for (int j = 0; j < kPer; ++j)
-        if (pos[j] != 0xffffffffu) stage[pos[j]] = __float_as_uint(z[j]);
-    __syncthreads();
+            for (int j = 0; j < kPer; ++j) z[j] = zs.in[h][at_of(j)];
+        }
+        __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < kPer; ++kk)
-        if (dst[kk] != 0xffffffffu) out_z[dst[kk]] = __uint_as_float(stage[tid + kk * kPartThreads]);
+        for (int j = 0; j < kPer; ++j)
+            if (pos[j] != 0xffffffffu) stage[pos[j]] = __float_as_uint(z[j]);
+        __syncthreads();
+        float* __restrict__ oz = zs.out[h];
+#pragma unroll
+        for (int kk = 0; kk < kPer; ++kk)
+            if (dst[kk] != 0xffffffffu) oz[dst[kk]] = __uint_as_float(stage[tid + kk * kPartThreads]);
+    }
 }
 
 // Last level: block L owns cells [L S, (L+1) S) (S <= 16384, a whole number of
 // the previous level's ranges, whose pairs sit at exactly the positions of
 // their cells) and the pairs at positions [L S, (L+1) S); it places z by cell
-// in LDS and writes the run of z_re contiguously.  OFF16: the pairs carry
+// in LDS and writes the run of z_re contiguously, for each of NZ histories
+// whose pairs share the same cells and positions.  OFF16: the pairs carry
 // their cell's offset inside its range of R cells (the second level's
 // sub-buckets), so pair i of the block belongs to cell floor(i/R) R + offset;
 // otherwise they carry the cell index.
 constexpr int kLeafMax = 16384;
 constexpr int kLeafThreads = 1024;
-template <bool OFF16>
-__global__ __launch_bounds__(kLeafThreads) void k_leaf_scatter(const void* __restrict__ in_cell,
-                                                               const float* __restrict__ in_z, long long n, unsigned S,
-                                                               unsigned R, double r_rinv, float* __restrict__ out) {
+template <bool OFF16, int NZ>
+__global__ __launch_bounds__(kLeafThreads) void k_leaf_scatter(const void* __restrict__ in_cell, ZSet zs, long long n,
+                                                               unsigned S, unsigned R, double r_rinv) {
     constexpr int kR = kLeafMax / kLeafThreads;
     __shared__ float zl[kLeafMax];
     const long long start = (long long)blockIdx.x * S;
     const long long left = n - start;
     const unsigned valid = left < (long long)S ? (unsigned)left : S;
-    unsigned c[kR];
+    unsigned rel[kR];  // the pair's cell relative to start, or ~0 (none)
     float z[kR];
     // every load in flight before any is used (clamped positions, no branch)
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const unsigned i = threadIdx.x + r * kLeafThreads;
         const long long at = start + (i < valid ? i : 0u);
+        long long c;
         if (OFF16) {
-            c[r] = reinterpret_cast<const unsigned short*>(in_cell)[at];
+            c = (long long)div_exact(i, R, r_rinv) * R + reinterpret_cast<const unsigned short*>(in_cell)[at];
         } else {
-            c[r] = reinterpret_cast<const unsigned*>(in_cell)[at];
+            c = (long long)reinterpret_cast<const unsigned*>(in_cell)[at] - start;
         }
-        z[r] = in_z[at];
+        rel[r] = (i < valid && c >= 0 && c < (long long)valid) ? (unsigned)c : 0xffffffffu;
+        z[r] = zs.in[0][at];
     }
+#pragma unroll 1
+    for (int h = 0; h < NZ; ++h) {
+        if (h > 0) {
+            __syncthreads();  // the previous history's run is written out
 #pragma unroll
-    for (int r = 0; r < kR; ++r) {
-        const unsigned i = threadIdx.x + r * kLeafThreads;
-        long long rel;
-        if (OFF16) {
-            rel = (long long)div_exact(i, R, r_rinv) * R + c[r];
-        } else {
-            rel = (long long)c[r] - start;
+            for (int r = 0; r < kR; ++r) {
+                const unsigned i = threadIdx.x + r * kLeafThreads;
+                z[r] = zs.in[h][start + (i < valid ? i : 0u)];
+            }
         }
-        if (i < valid && rel >= 0 && rel < (long long)valid) zl[rel] = z[r];
-    }
-    __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kR; ++r) {
-        const unsigned i = threadIdx.x + r * kLeafThreads;
-        if (i < valid) out[start + i] = zl[i];
+        for (int r = 0; r < kR; ++r)
+            if (rel[r] != 0xffffffffu) zl[rel[r]] = z[r];
+        __syncthreads();
+        float* __restrict__ out = zs.out[h];
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const unsigned i = threadIdx.x + r * kLeafThreads;
+            if (i < valid) out[start + i] = zl[i];
+        }
     }
 }
 
@@ -867,10 +889,15 @@ int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, flo
                  block_excl, n_tiles, sum_tpb);
     AMBER_LAUNCH(p, "match_block_prefix", k_block_prefix, dim3(1), dim3(kPrefixThreads), s, block_excl, n_blocks, ctrl);
     const double rinv = 1.0 / (double)S1;
-    for (int g = 0; g * kGroup < n_hist; ++g) {
-        const int h0 = g * kGroup;
+    // Groups of up to kGroup histories, the short one first: after the last
+    // group's scan the rank order and sorted weights are no longer needed, so
+    // their buffers hold that group's second-level z fields and its histories
+    // share one second-level pass and one leaf pass.
+    const int first = (n_hist % kGroup) ? n_hist % kGroup : kGroup;
+    for (int g = 0, h0 = 0; h0 < n_hist; h0 += (g == 0 ? first : kGroup), ++g) {
         HistArgs hs{};
-        hs.n = std::min(kGroup, n_hist - h0);
+        hs.n = g == 0 ? first : kGroup;
+        const bool last = h0 + hs.n == n_hist;
         for (int i = 0; i < hs.n; ++i) {
             const amber_weibull& w = hist[h0 + i];
             hs.h[i] = HistArg{w.a_w, w.b_w, 1.0 / w.c_w, w.h, w.z_top, (long long)(w.table_n - 1), w.d_table,
@@ -893,16 +920,56 @@ int match_scan(const amber_plan_s* p, const amber_weibull* hist, int n_hist, flo
             default: AMBER_SCAN(3, true) break;
         }
 #undef AMBER_SCAN
-        for (int i = 0; i < hs.n; ++i) {
-            if (two_level) {
-                AMBER_LAUNCH(p, "match_clear", k_clear, dim3(256), dim3(256), s, fill2, 65536);
-                AMBER_LAUNCH(p, "match_partition2", k_partition2, dim3(kL1 * tpb), dim3(kPartThreads), s, p1_idx,
-                             p1_z[i], n, fill2, S1, S2, s2_rinv, tpb, p2_off, p2_z);
-                AMBER_LAUNCH(p, "match_leaf_scatter", k_leaf_scatter<true>, dim3(leaf_blocks), dim3(kLeafThreads), s,
-                             p2_off, p2_z, n, leaf, S2, s2_rinv, d_zre[h0 + i]);
+        // the group's z fields in (first level) and out (second level / z_re)
+        auto zset = [&](int i0, int cnt, float* const* mid) {
+            ZSet z{};
+            for (int i = 0; i < cnt; ++i) {
+                z.in[i] = mid ? mid[i] : p1_z[i0 + i];
+                z.out[i] = mid ? mid[i] : d_zre[h0 + i0 + i];
+            }
+            return z;
+        };
+        auto second_level = [&](int nz, const ZSet& z) {
+            AMBER_LAUNCH(p, "match_clear", k_clear, dim3(256), dim3(256), s, fill2, 65536);
+            switch (nz) {
+                case 1: AMBER_LAUNCH(p, "match_partition2", k_partition2<1>, dim3(kL1 * tpb), dim3(kPartThreads), s,
+                                     p1_idx, z, n, fill2, S1, S2, s2_rinv, tpb, p2_off); break;
+                case 2: AMBER_LAUNCH(p, "match_partition2", k_partition2<2>, dim3(kL1 * tpb), dim3(kPartThreads), s,
+                                     p1_idx, z, n, fill2, S1, S2, s2_rinv, tpb, p2_off); break;
+                default: AMBER_LAUNCH(p, "match_partition2", k_partition2<3>, dim3(kL1 * tpb), dim3(kPartThreads), s,
+                                      p1_idx, z, n, fill2, S1, S2, s2_rinv, tpb, p2_off); break;
+            }
+        };
+        auto leaf_pass = [&](bool off16, const void* cells, int nz, const ZSet& z) {
+#define AMBER_LEAF(O, NZV)                                                                                             AMBER_LAUNCH(p, "match_leaf_scatter", (k_leaf_scatter<O, NZV>), dim3(leaf_blocks), dim3(kLeafThreads), s, cells,                  z, n, leaf, S2, s2_rinv)
+            if (off16) {
+                if (nz == 1) AMBER_LEAF(true, 1); else if (nz == 2) AMBER_LEAF(true, 2); else AMBER_LEAF(true, 3);
             } else {
-                AMBER_LAUNCH(p, "match_leaf_scatter", k_leaf_scatter<false>, dim3(leaf_blocks), dim3(kLeafThreads), s,
-                             p1_idx, p1_z[i], n, leaf, S2, s2_rinv, d_zre[h0 + i]);
+                if (nz == 1) AMBER_LEAF(false, 1); else if (nz == 2) AMBER_LEAF(false, 2); else AMBER_LEAF(false, 3);
+            }
+#undef AMBER_LEAF
+        };
+        if (!two_level) {
+            leaf_pass(false, p1_idx, hs.n, zset(0, hs.n, nullptr));
+        } else if (last && hs.n > 1) {
+            float* mid[kGroup] = {p2_z, reinterpret_cast<float*>(ws + L.vals[0]), reinterpret_cast<float*>(ws + L.wts[0])};
+            ZSet z2 = zset(0, hs.n, nullptr);  // first level in, second level out
+            ZSet zl = zset(0, hs.n, nullptr);  // second level in, z_re out
+            for (int i = 0; i < hs.n; ++i) {
+                z2.out[i] = mid[i];
+                zl.in[i] = mid[i];
+            }
+            second_level(hs.n, z2);
+            leaf_pass(true, p2_off, hs.n, zl);
+        } else {
+            for (int i = 0; i < hs.n; ++i) {
+                ZSet z2{}, zl{};
+                z2.in[0] = p1_z[i];
+                z2.out[0] = p2_z;
+                zl.in[0] = p2_z;
+                zl.out[0] = d_zre[h0 + i];
+                second_level(1, z2);
+                leaf_pass(true, p2_off, 1, zl);
             }
         }
     }
