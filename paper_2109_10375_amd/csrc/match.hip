@@ -442,9 +442,12 @@ __global__ __launch_bounds__(kPrefixThreads) void k_block_prefix(u128* __restric
 // fill[b] (cleared before the launch) counts the slots of bucket b handed out.
 // With several histories the plain kernel is held to three waves per SIMD
 // (168 registers, a few spilled): faster than two waves at 178 (at 1024^3
-// with three histories 13.3 vs 16.7 ms) and than four at 128 (17.7 ms).
+// with three histories 13.3 vs 16.7 ms) and than four at 128 (17.7 ms).  The
+// growth kernel for one history runs at five (96 registers: 27.5 vs 28.3 ms
+// at four; six was slower).
 template <int NH, bool WIDE, bool GROWTH>
-__global__ __launch_bounds__(kScanThreads, (NH > 1 && !GROWTH) ? 3 : 1) void k_scan_partition(
+__global__ __launch_bounds__(kScanThreads, (NH > 1 && !GROWTH) ? 3 : ((NH == 1 && GROWTH) ? 5 : 1))
+void k_scan_partition(
     const unsigned* __restrict__ perm, const float* __restrict__ w_sorted, long long n, Ctrl* ctrl,
     const u128* __restrict__ local, const u128* __restrict__ block_excl, unsigned* __restrict__ fill,
     int tpb, unsigned bucket_size, double bucket_rinv, HistArgs hs, unsigned* __restrict__ part_idx,
