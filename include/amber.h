@@ -30,8 +30,9 @@
  *   - errors are returned as negative codes and never abort.  Argument errors
  *     are found on the host before anything is enqueued.  Data errors found on
  *     the device (NaN intensity, non-positive or non-finite weights, a mass sum
- *     wider than 127 bits) set bits of a status word in the workspace, read by
- *     amber_status(); the outputs of such a call are unspecified.
+ *     wider than 127 bits) set bits of the plan's status word, which keeps them
+ *     until amber_status() reads and clears it; the outputs of such a call are
+ *     unspecified.
  */
 #ifndef AMBER_H
 #define AMBER_H
@@ -74,7 +75,9 @@ typedef struct {
  *   table_n = T + 1 with T = ceil((z_top - a_w) / h); node j is z_j = a_w + j h
  *             and holds X_j = exp(-((z_j - a_w)/b_w)^c_w) (FP64)
  * d_table must point to T + 1 doubles on the device holding exactly the values
- * written by amber_weibull_table() for this struct.
+ * written by amber_weibull_table() for this struct (amber_history_prepare
+ * fills such a buffer).  amber_zre rejects a struct whose h, z_top or table_n
+ * differ from what amber_weibull_from_coeffs gives for its coefficients.
  * d_growth selects the matching equation (Sec. 3.4.2): NULL weights every cell
  * by its gas mass 1 + delta at z_mid; otherwise it points to T + 1 pairs
  * (X_j, G_j) of device doubles (2 (T + 1) doubles, 16-byte aligned, as written
@@ -89,7 +92,7 @@ typedef struct {
     const double* d_growth;
 } amber_weibull;
 
-/* ---- host-side helpers (no device work) -------------------------------- */
+/* ---- history helpers (host work; the two prepare calls also copy to the device) -- */
 
 const char* amber_version(void);
 const char* amber_strerror(int code);
@@ -107,6 +110,28 @@ int amber_weibull_from_coeffs(double a_w, double b_w, double c_w, amber_weibull*
 /* Writes the T + 1 inversion-table values X_j into host_table (n_entries must
  * equal w->table_n).  The caller copies them to the device and sets d_table. */
 int amber_weibull_table(const amber_weibull* w, double* host_table, int64_t n_entries);
+
+/* Sec. 3.1 and Sec. 3.1.2 on the device: amber_weibull_fit of hist, then the
+ * T + 1 inversion-table values of amber_weibull_table copied into the caller's
+ * device buffer d_table_buf (buf_bytes >= 8 table_n bytes) on `stream`; *out
+ * receives the fitted history with d_table = d_table_buf (d_growth NULL).
+ * Blocks the host until the copy has completed (the values are built in
+ * library-owned host memory that is freed before returning).  With d_table_buf
+ * NULL only *out is filled (d_table NULL): table_n gives the buffer size.
+ * Errors: those of amber_weibull_fit; AMBER_E_WORKSPACE when buf_bytes is too
+ * small; AMBER_E_HIP when the copy fails (nothing is written to *out). */
+int amber_history_prepare(const amber_history* hist, amber_weibull* out, void* d_table_buf, size_t buf_bytes,
+                          void* stream);
+
+/* Sec. 3.4.2 with growth-rescaled overdensities: the (X_j, G_j) pairs of
+ * amber_growth_table for the fitted history *w copied into the caller's device
+ * buffer d_pairs_buf (16-byte aligned, buf_bytes >= 16 table_n) on `stream`;
+ * sets w->d_growth = d_pairs_buf.  Blocks the host until the copy has
+ * completed.  AMBER_E_ARG for a misaligned buffer or a table geometry that is
+ * not amber_weibull_from_coeffs(a_w, b_w, c_w)'s; AMBER_E_WORKSPACE when the
+ * buffer is too small; AMBER_E_HIP when the copy fails (w is left unchanged). */
+int amber_growth_prepare(amber_weibull* w, double z_mid, double omega_m, void* d_pairs_buf, size_t buf_bytes,
+                         void* stream);
 
 /* Linear growth factor ratio at the table nodes, G_j = D(a_w + j h)/D(z_mid),
  * j = 0..T, for a flat universe of matter density omega_m (0 < omega_m <= 1)
@@ -128,8 +153,10 @@ int amber_plan_create(amber_plan* out, int n, double box_len);
 void amber_plan_destroy(amber_plan plan);
 
 /* Device workspace needed by amber_radiation (with n_lmfp mean free paths),
- * amber_rank and amber_zre on this plan. */
-size_t amber_workspace_bytes(amber_plan plan, int n_lmfp);
+ * amber_rank and amber_zre (with n_hist histories; 0 for radiation or rank
+ * only) on this plan.  0 for a NULL plan, n_lmfp outside 0..64 or n_hist
+ * outside 0..8. */
+size_t amber_workspace_bytes(amber_plan plan, int n_lmfp, int n_hist);
 
 /* ---- device stages ------------------------------------------------------ */
 
@@ -241,9 +268,12 @@ int amber_zre(amber_plan plan, const float* d_J, const float* d_w,
               const amber_weibull* hist, int n_hist, float* const* d_zre,
               void* d_ws, size_t ws_bytes, void* stream);
 
-/* Waits for `stream`, then returns (and clears) the device status bits of the
- * last calls that used this workspace in *status. */
-int amber_status(amber_plan plan, void* d_ws, void* stream, unsigned* status);
+/* Waits for `stream`, then returns in *status and clears the device status
+ * bits (AMBER_STATUS_*) of every ranking and matching call on this plan since
+ * the plan was created or amber_status last cleared them, whatever workspace
+ * the calls used.  Calls still in flight on other streams are reported by a
+ * later amber_status once they have completed. */
+int amber_status(amber_plan plan, void* stream, unsigned* status);
 
 /* ---- two-point statistics (Sec. 2.3) ------------------------------------- */
 

@@ -75,7 +75,8 @@ def lib():
         L.oracle_growth.argtypes = [d, d]
         L.oracle_growth.restype = d
         L.oracle_growth_table.argtypes = [d, d, i64, d, d, p]
-        L.oracle_zre_growth_f32.argtypes = [i64, p, p, d, d, i64, d, p, p, p, p]
+        L.oracle_zre_growth_f32.argtypes = [i64, p, p, d, d, i64, d, p, p, p, p, i64, p, p, p]
+        L.oracle_gauss_legendre.argtypes = [i, p, p]
         L.oracle_rank_f32.argtypes = [i64, p, p]
         L.oracle_rank_f64.argtypes = [i64, p, p]
         L.oracle_mass_fraction.argtypes = [i64, p, p, p]
@@ -266,18 +267,35 @@ def growth_table(H: "History", z_mid: float, omega_m: float = OMEGA_M) -> np.nda
     return G
 
 
-def zre_growth(J: np.ndarray, w: np.ndarray, H: "History", G: np.ndarray):
+def gauss_legendre(n: int) -> tuple[np.ndarray, np.ndarray]:
+    """Nodes and weights of the n-point Gauss-Legendre rule on [-1, 1]."""
+    x = np.empty(n)
+    w = np.empty(n)
+    _check(lib().oracle_gauss_legendre(int(n), _ptr(x), _ptr(w)), "gauss_legendre")
+    return x, w
+
+
+def zre_growth(J: np.ndarray, w: np.ndarray, H: "History", G: np.ndarray, ranks=None):
     """Growth-rescaled abundance matching (Sec. 3.4.2 with the growth factor,
-    readings G1, G2): returns (z_re FP32, z_re FP64)."""
+    readings G1, G2): returns (z_re FP32, z_re FP64).  With ``ranks`` (rank
+    positions, 0 = brightest) only those ranks are matched and the result is
+    (z FP32 per rank, cell index per rank)."""
     j = np.ascontiguousarray(J, dtype=np.float32).reshape(-1)
     ww = np.ascontiguousarray(w, dtype=np.float32).reshape(-1)
     Gc = np.ascontiguousarray(G, dtype=np.float64)
     if Gc.size != H.T + 1:
         raise ValueError("growth table must have T + 1 entries")
+    if ranks is not None:
+        sel = np.ascontiguousarray(np.asarray(ranks, dtype=np.int64).reshape(-1))
+        zs = np.empty(sel.size, dtype=np.float32)
+        cells = np.empty(sel.size, dtype=np.uint32)
+        _check(lib().oracle_zre_growth_f32(j.size, _ptr(j), _ptr(ww), H.a, H.h, H.T, H.z_top, _ptr(H.X), _ptr(Gc),
+                                           None, None, sel.size, _ptr(sel), _ptr(zs), _ptr(cells)), "zre_growth")
+        return zs, cells
     z32 = np.empty(j.size, dtype=np.float32)
     z64 = np.empty(j.size, dtype=np.float64)
     _check(lib().oracle_zre_growth_f32(j.size, _ptr(j), _ptr(ww), H.a, H.h, H.T, H.z_top, _ptr(H.X), _ptr(Gc),
-                                       _ptr(z32), _ptr(z64)), "zre_growth")
+                                       _ptr(z32), _ptr(z64), 0, None, None, None), "zre_growth")
     return z32.reshape(J.shape), z64.reshape(J.shape)
 
 
@@ -374,3 +392,47 @@ def invert(F, hist: History, mode: int = CONTRACT) -> np.ndarray:
 
 def u128_to_double(v: int) -> float:
     return lib().oracle_u128_to_double((v >> 64) & ((1 << 64) - 1), v & ((1 << 64) - 1))
+
+
+def zre_per_cell_check(J32: np.ndarray, J64: np.ndarray, w: np.ndarray, hist: History, z_gpu: np.ndarray,
+                       tol: float = 1e-4) -> dict:
+    """End-to-end check of a z_re field matched from an FP32 intensity field
+    J32 (Sec. 3.4.2), cell by cell, against the FP64 oracle:
+
+      1. every cell is within ``tol`` of the exact-mode match of the same FP32
+         field (rank order of J32, exact cumulative mass, closed-form
+         inversion): the matching itself is right in every cell;
+      2. against the exact-mode match of the FP64 field J64, a cell can differ
+         by more than ``tol`` only where its exact ionized-mass fraction F
+         differs between the two rank orders (the FP32 field orders some
+         nearly equal intensities differently); such cells are counted.
+
+    Raises AssertionError naming the first failing cell; returns statistics."""
+    shape = J32.shape
+    wf = np.ascontiguousarray(w, dtype=np.float32).reshape(-1)
+    zg = np.asarray(z_gpu, dtype=np.float64).reshape(-1)
+    _, z32x = zre(np.ascontiguousarray(J32, dtype=np.float32), wf.reshape(shape), hist, mode=EXACT)
+    err32 = np.abs(zg - z32x.reshape(-1))
+    bad = np.nonzero(err32 > tol)[0]
+    assert bad.size == 0, (f"cell {int(bad[0])}: z {zg[bad[0]]!r} vs exact match of the same FP32 field "
+                           f"{z32x.reshape(-1)[bad[0]]!r} ({bad.size} cells beyond {tol})")
+    _, z64x = zre(np.ascontiguousarray(J64, dtype=np.float64), wf.reshape(shape), hist, mode=EXACT)
+    err64 = np.abs(zg - z64x.reshape(-1))
+    pg = rank(np.ascontiguousarray(J32, dtype=np.float32))
+    po = rank(np.ascontiguousarray(J64, dtype=np.float64))
+    Fg = np.empty(pg.size)
+    Fo = np.empty(po.size)
+    Fg[pg] = mass_fraction(pg, wf)
+    Fo[po] = mass_fraction(po, wf)
+    over = err64 > tol
+    unexplained = np.nonzero(over & (Fg == Fo))[0]
+    assert unexplained.size == 0, (f"cell {int(unexplained[0])}: beyond {tol} of the FP64 match with the "
+                                   f"same ionized-mass fraction in both orders")
+    pos_g = np.empty_like(pg)
+    pos_g[pg] = np.arange(pg.size, dtype=np.uint32)
+    pos_o = np.empty_like(po)
+    pos_o[po] = np.arange(po.size, dtype=np.uint32)
+    disp = np.abs(pos_g.astype(np.int64) - pos_o.astype(np.int64))
+    return {"max_err_same_field": float(err32.max()), "frac_within_tol_fp64": float(np.mean(~over)),
+            "cells_over_tol_fp64": int(over.sum()), "max_err_fp64": float(err64.max()),
+            "max_rank_displacement": int(disp.max()), "cells_moved": int(np.sum(disp > 0))}

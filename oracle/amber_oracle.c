@@ -67,8 +67,9 @@
  *      G_j = D(z_j)/D(z_mid) is tabulated at the inversion-table nodes;
  *   G2 with growth, rank n solves m_n(z)/M(z) = x_i(z) with the growth-weighted
  *      masses m_n = n (1 - g) + g C_n (C_n the exact prefix of w = 1 + delta),
- *      evaluated at the nodes with g = G_j, located by bisection over the node
- *      index and interpolated linearly between the bracketing nodes.
+ *      evaluated at the nodes with g = G_j; the root's bracket ends at the
+ *      first node, walking up from z = a_w, where the growth-weighted ionized
+ *      fraction exceeds x_i, and z is interpolated linearly inside it.
  *
  * Parity pins for each routine live in tests/test_oracle_*.py.
  */
@@ -641,7 +642,7 @@ struct mass_scale { int qmin; u128 total; };
 static int mass_scale_of(int64_t n, const float* w, struct mass_scale* ms) {
     int qmin = 1 << 30;
     for (int64_t i = 0; i < n; ++i) {
-        uint64_t m; int q;
+        uint64_t m = 0; int q = 0;
         if (weight_parts(w[i], &m, &q) != OR_OK) return OR_E_DATA;
         if (q < qmin) qmin = q;
     }
@@ -649,7 +650,7 @@ static int mass_scale_of(int64_t n, const float* w, struct mass_scale* ms) {
     u128 tot = 0;
     const u128 lim = (u128)1 << 127;
     for (int64_t i = 0; i < n; ++i) {
-        uint64_t m; int q;
+        uint64_t m = 0; int q = 0;
         weight_parts(w[i], &m, &q);
         int sh = q - qmin;
         if (sh + bit_length64(m) > 127) return OR_E_RANGE;
@@ -663,7 +664,7 @@ static int mass_scale_of(int64_t n, const float* w, struct mass_scale* ms) {
 }
 
 static u128 scaled_weight(float wf, int qmin) {
-    uint64_t m; int q;
+    uint64_t m = 0; int q = qmin;
     weight_parts(wf, &m, &q);
     return (u128)m << (q - qmin);
 }
@@ -711,33 +712,86 @@ static double invert_table(double F, double a, double h, int64_t T, double z_top
 /* Growth-rescaled matching: Sec. 3.4.2 with delta_m(z) = D(z)/D(z_mid) delta_m */
 /* ------------------------------------------------------------------------ */
 
-/* Linear growth factor (reading G1): for a flat universe with matter density
- * omega_m and a cosmological constant 1 - omega_m the growing mode is
- *   D(a) = a 2F1(1/3, 1; 11/6; x),  x = -(1 - omega_m)/omega_m a^3,
- * which equals a while matter dominates.  Pfaff's transformation
- *   2F1(1/3, 1; 11/6; x) = (1 - x)^-1 2F1(3/2, 1; 11/6; x/(x - 1))
- * turns x in (-inf, 0] into y = x/(x - 1) in [0, 1), where the power series
- * sum_k (3/2)_k / (11/6)_k y^k converges; it is summed until a term no longer
- * changes the sum. */
-double oracle_growth(double z, double omega_m) {
-    const double a = 1.0 / (1.0 + z);
-    const double x = -(1.0 - omega_m) / omega_m * (a * a * a);
-    const double y = x / (x - 1.0);
-    double term = 1.0, sum = 1.0;
-    for (int k = 0; k < 100000; ++k) {
-        term = term * ((1.5 + (double)k) / (11.0 / 6.0 + (double)k)) * y;
-        const double next = sum + term;
-        if (next == sum) break;
-        sum = next;
+/* Gauss-Legendre rule of order n on [-1, 1]: the nodes are the roots of the
+ * Legendre polynomial P_n, found by Newton's method from the standard
+ * asymptotic starting values, with P_n and P_n' from the three-term recurrence
+ * (k + 1) P_{k+1} = (2k + 1) x P_k - k P_{k-1}; the weights are
+ * 2 / ((1 - x^2) P_n'(x)^2).  A textbook construction, exact for polynomials
+ * of degree up to 2n - 1. */
+int oracle_gauss_legendre(int n, double* x, double* w) {
+    if (n < 1 || n > 512) return OR_E_ARG;
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double t = cos(3.14159265358979323846 * ((double)i + 0.75) / ((double)n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = t;  /* P_0, P_1; after the loop P_{n-1}, P_n */
+            for (int k = 1; k < n; ++k) {
+                const double p2 = ((2.0 * k + 1.0) * t * p1 - (double)k * p0) / ((double)k + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = (double)n * (t * p1 - p0) / (t * t - 1.0);
+            const double step = p1 / dp;
+            t -= step;
+            if (fabs(step) <= 1e-16 * (1.0 + fabs(t))) {
+                /* P_n' at the updated node */
+                p0 = 1.0;
+                p1 = t;
+                for (int k = 1; k < n; ++k) {
+                    const double p2 = ((2.0 * k + 1.0) * t * p1 - (double)k * p0) / ((double)k + 1.0);
+                    p0 = p1;
+                    p1 = p2;
+                }
+                dp = (double)n * (t * p1 - p0) / (t * t - 1.0);
+                break;
+            }
+        }
+        x[i] = -t;
+        x[n - 1 - i] = t;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - t * t) * dp * dp);
     }
-    return a * (sum / (1.0 - x));
+    if (n % 2 == 1) x[n / 2] = 0.0;
+    return OR_OK;
+}
+
+/* Linear growth factor (reading G1): the growing mode of a flat universe of
+ * matter density omega_m and a cosmological constant 1 - omega_m,
+ *   D(a) = (5 omega_m / 2) E(a) int_0^a da' / (a' E(a'))^3,
+ *   E(a) = sqrt(omega_m a^-3 + 1 - omega_m),
+ * normalised so that D = a while matter dominates.  With a' = s^2 the
+ * integrand becomes the smooth 2 s^4 / (omega_m + (1 - omega_m) s^6)^(3/2) on
+ * [0, sqrt(a)], integrated by one 64-point Gauss-Legendre rule (gx, gw). */
+#define GROWTH_GL 64
+static double growth_quadrature(double z, double omega_m, const double* gx, const double* gw) {
+    const double a = 1.0 / (1.0 + z);
+    const double r = sqrt(a);
+    const double lam = 1.0 - omega_m;
+    double sum = 0.0;
+    for (int i = 0; i < GROWTH_GL; ++i) {
+        const double s = 0.5 * r * (gx[i] + 1.0);
+        const double s2 = s * s;
+        const double q = omega_m + lam * s2 * s2 * s2;
+        sum += gw[i] * (2.0 * s2 * s2 / (q * sqrt(q)));
+    }
+    const double integral = 0.5 * r * sum;
+    const double E = sqrt(omega_m / (a * a * a) + lam);
+    return 2.5 * omega_m * E * integral;
+}
+
+double oracle_growth(double z, double omega_m) {
+    double gx[GROWTH_GL], gw[GROWTH_GL];
+    oracle_gauss_legendre(GROWTH_GL, gx, gw);
+    return growth_quadrature(z, omega_m, gx, gw);
 }
 
 /* G_j = D(z_j)/D(z_mid) at the table nodes z_j = a + j h, j = 0..T. */
 int oracle_growth_table(double a, double h, int64_t T, double z_mid, double omega_m, double* G) {
     if (!(h > 0.0) || T < 1 || !(omega_m > 0.0) || !(omega_m <= 1.0)) return OR_E_ARG;
-    const double dmid = oracle_growth(z_mid, omega_m);
-    for (int64_t j = 0; j <= T; ++j) G[j] = oracle_growth(a + (double)j * h, omega_m) / dmid;
+    double gx[GROWTH_GL], gw[GROWTH_GL];
+    oracle_gauss_legendre(GROWTH_GL, gx, gw);
+    const double dmid = growth_quadrature(z_mid, omega_m, gx, gw);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j <= T; ++j) G[j] = growth_quadrature(a + (double)j * h, omega_m, gx, gw) / dmid;
     return OR_OK;
 }
 
@@ -752,37 +806,43 @@ static double growth_gap(double ks, double ns, double cn, double cN, double G, d
     return m / M - X;
 }
 
-/* z of one rank: z = a if h_0 > 0, z_top if h_T <= 0, else bisection on the
- * node index keeping h_lo <= 0 < h_hi, then z = z_lo + t (z_hi - z_lo) with
- * t = -h_lo / (h_hi - h_lo), clamped to z_top. */
+/* z of one rank (reading G2): walking up the nodes from z_0 = a_w, the first
+ * node j with h_j > 0.  None: z = z_top.  j = 0: z = a_w.  Otherwise the
+ * bracket is (j - 1, j) and z = z_lo + t (z_hi - z_lo), t = -h_lo / (h_hi - h_lo),
+ * clamped to z_top. */
 static double invert_growth(double ks, double ns, double cn, double cN, double a, double h, int64_t T,
                             double z_top, const double* X, const double* G) {
-    const double h0 = growth_gap(ks, ns, cn, cN, G[0], X[0]);
-    if (h0 > 0.0) return a;
-    const double hT = growth_gap(ks, ns, cn, cN, G[T], X[T]);
-    if (!(hT > 0.0)) return z_top;
-    int64_t lo = 0, hi = T;
-    double hlo = h0, hhi = hT;
-    while (hi - lo > 1) {
-        const int64_t mid = lo + (hi - lo) / 2;
-        const double hm = growth_gap(ks, ns, cn, cN, G[mid], X[mid]);
-        if (hm <= 0.0) { lo = mid; hlo = hm; } else { hi = mid; hhi = hm; }
+    int64_t j = 0;
+    double hj = growth_gap(ks, ns, cn, cN, G[0], X[0]);
+    if (hj > 0.0) return a;
+    double hprev = hj;
+    for (j = 1; j <= T; ++j) {
+        hj = growth_gap(ks, ns, cn, cN, G[j], X[j]);
+        if (hj > 0.0) break;
+        hprev = hj;
     }
-    const double zl = a + (double)lo * h;
-    const double zh = a + (double)hi * h;
-    const double t = -hlo / (hhi - hlo);
+    if (j > T) return z_top;
+    const double zl = a + (double)(j - 1) * h;
+    const double zh = a + (double)j * h;
+    const double t = -hprev / (hj - hprev);
     const double z = zl + t * (zh - zl);
     return (z < z_top) ? z : z_top;
 }
 
 /* Full growth-rescaled match (readings G1, G2): ranking as in oracle_zre_*,
- * exact prefix masses, per-rank bisection on the tables X and G. */
+ * exact prefix masses, then each rank's node walk (independent per rank).
+ * With n_sel > 0 only the ranks listed in sel are matched: z_sel[i] receives
+ * the z of rank sel[i] and cell_sel[i] its cell (zre and zre64 are unused). */
 int oracle_zre_growth_f32(int64_t n, const float* J, const float* w, double a, double h, int64_t T,
-                          double z_top, const double* X, const double* G, float* zre, double* zre64) {
+                          double z_top, const double* X, const double* G, float* zre, double* zre64,
+                          int64_t n_sel, const int64_t* sel, float* z_sel, uint32_t* cell_sel) {
     uint32_t* perm = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    double* cn = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     struct mass_scale ms;
     int rc = rank_any(n, J, NULL, perm);
     if (rc == OR_OK) rc = mass_scale_of(n, w, &ms);
+    for (int64_t i = 0; rc == OR_OK && i < n_sel; ++i)
+        if (sel[i] < 0 || sel[i] >= n) rc = OR_E_ARG;
     if (rc == OR_OK) {
         const double s = ldexp(1.0, -ms.qmin);
         const double cN = (double)ms.total;
@@ -790,11 +850,25 @@ int oracle_zre_growth_f32(int64_t n, const float* J, const float* w, double a, d
         u128 c = 0;
         for (int64_t k = 0; k < n; ++k) {
             c += scaled_weight(w[perm[k]], ms.qmin);
-            const double z = invert_growth((double)(k + 1) * s, ns, (double)c, cN, a, h, T, z_top, X, G);
-            if (zre) zre[perm[k]] = (float)z;
-            if (zre64) zre64[perm[k]] = z;
+            cn[k] = (double)c;
+        }
+        if (n_sel > 0) {
+#pragma omp parallel for schedule(dynamic, 16)
+            for (int64_t i = 0; i < n_sel; ++i) {
+                const int64_t k = sel[i];
+                z_sel[i] = (float)invert_growth((double)(k + 1) * s, ns, cn[k], cN, a, h, T, z_top, X, G);
+                cell_sel[i] = perm[k];
+            }
+        } else {
+#pragma omp parallel for schedule(dynamic, 64)
+            for (int64_t k = 0; k < n; ++k) {
+                const double z = invert_growth((double)(k + 1) * s, ns, cn[k], cN, a, h, T, z_top, X, G);
+                if (zre) zre[perm[k]] = (float)z;
+                if (zre64) zre64[perm[k]] = z;
+            }
         }
     }
+    free(cn);
     free(perm);
     return rc;
 }

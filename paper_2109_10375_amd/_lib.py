@@ -26,7 +26,7 @@ SYMBOLS = [
     "amber_profile_end", "amber_batch_workspace_bytes", "amber_batch_run", "amber_spectra_workspace_bytes",
     "amber_spectra", "amber_growth_table", "amber_halo_workspace_bytes", "amber_radiation_from_halos",
     "amber_fft_schedules", "amber_fft_schedule_info", "amber_plan_set_schedule", "amber_plan_get_schedule",
-    "amber_plan_tune",
+    "amber_plan_tune", "amber_history_prepare", "amber_growth_prepare",
 ]
 ASSIGN_NGP, ASSIGN_CIC, ASSIGN_TSC = 1, 2, 3
 FIELD_RAW, FIELD_OVERDENSITY, FIELD_REDSHIFT = 0, 1, 2
@@ -91,12 +91,14 @@ def lib() -> ctypes.CDLL:
         L.amber_plan_create.argtypes = [ctypes.POINTER(vp), i, d]
         L.amber_plan_destroy.argtypes = [vp]
         L.amber_plan_destroy.restype = None
-        L.amber_workspace_bytes.argtypes = [vp, i]
+        L.amber_workspace_bytes.argtypes = [vp, i, i]
         L.amber_workspace_bytes.restype = sz
         L.amber_radiation.argtypes = [vp, vp, ctypes.POINTER(d), i, ctypes.POINTER(vp), vp, sz, vp]
         L.amber_rank.argtypes = [vp, vp, vp, vp, sz, vp]
         L.amber_zre.argtypes = [vp, vp, vp, ctypes.POINTER(AmberWeibull), i, ctypes.POINTER(vp), vp, sz, vp]
-        L.amber_status.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_uint)]
+        L.amber_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_uint)]
+        L.amber_history_prepare.argtypes = [ctypes.POINTER(AmberHistory), ctypes.POINTER(AmberWeibull), vp, sz, vp]
+        L.amber_growth_prepare.argtypes = [ctypes.POINTER(AmberWeibull), d, d, vp, sz, vp]
         L.amber_profile_begin.argtypes = [vp, i]
         L.amber_profile_end.argtypes = [vp, ctypes.POINTER(AmberKernelTime), i, ctypes.POINTER(i)]
         L.amber_batch_workspace_bytes.argtypes = [ctypes.POINTER(AmberBatchItem), i]
@@ -143,10 +145,17 @@ class History:
 
     @classmethod
     def from_params(cls, z_mid, delta_z, a_z, x_ear=0.0, x_mid=0.0, x_lat=0.0, device=None):
+        """amber_history_prepare: the fit and its device table in one call."""
         h = AmberHistory(z_mid, delta_z, a_z, x_ear, x_mid, x_lat)
         w = AmberWeibull()
-        _check(lib().amber_weibull_fit(ctypes.byref(h), ctypes.byref(w)), "amber_weibull_fit")
-        return cls(w, device)
+        _check(lib().amber_history_prepare(ctypes.byref(h), ctypes.byref(w), None, 0, None), "amber_history_prepare")
+        table = torch.empty(w.table_n, dtype=torch.float64, device=device or torch.device("cuda"))
+        _check(lib().amber_history_prepare(ctypes.byref(h), ctypes.byref(w), ctypes.c_void_p(table.data_ptr()),
+                                           table.numel() * 8, _stream()), "amber_history_prepare")
+        obj = cls.__new__(cls)
+        obj.w = w
+        obj.table = table
+        return obj
 
     @classmethod
     def from_coeffs(cls, a_w, b_w, c_w, device=None):
@@ -173,12 +182,27 @@ class History:
         h = History.__new__(History)
         h.w = w
         h.table = self.table
-        host = torch.empty(2 * w.table_n, dtype=torch.float64)
-        _check(lib().amber_growth_table(ctypes.byref(w), float(z_mid), float(omega_m),
-                                        ctypes.c_void_p(host.data_ptr()), w.table_n), "amber_growth_table")
-        h.growth = host.to(self.table.device)
+        h.growth = torch.empty(2 * w.table_n, dtype=torch.float64, device=self.table.device)
         h.w.d_table = self.table.data_ptr()
-        h.w.d_growth = h.growth.data_ptr()
+        _check(lib().amber_growth_prepare(ctypes.byref(h.w), float(z_mid), float(omega_m),
+                                          ctypes.c_void_p(h.growth.data_ptr()), h.growth.numel() * 8, _stream()),
+               "amber_growth_prepare")
+        return h
+
+    def with_growth_pairs(self, pairs: torch.Tensor) -> "History":
+        """The same history matched with a caller-built growth table: a
+        contiguous CUDA float64 tensor of 2 table_n values, the pairs
+        (X_j, G_j) that amber_weibull.d_growth points to."""
+        _dev_ptr(pairs, torch.float64, 2 * self.w.table_n, "growth pairs")
+        if pairs.data_ptr() % 16:
+            raise ValueError("growth pairs: the device table must be 16-byte aligned")
+        w = AmberWeibull.from_buffer_copy(self.w)
+        h = History.__new__(History)
+        h.w = w
+        h.table = self.table
+        h.growth = pairs
+        h.w.d_table = self.table.data_ptr()
+        h.w.d_growth = pairs.data_ptr()
         return h
 
     @staticmethod
@@ -226,8 +250,8 @@ class Plan:
             _lib.amber_plan_destroy(h)
             self._h = None
 
-    def workspace_bytes(self, n_lmfp: int = 1) -> int:
-        return int(lib().amber_workspace_bytes(self._h, int(n_lmfp)))
+    def workspace_bytes(self, n_lmfp: int = 1, n_hist: int = 1) -> int:
+        return int(lib().amber_workspace_bytes(self._h, int(n_lmfp), int(n_hist)))
 
     def workspace(self, n_lmfp: int = 1) -> torch.Tensor:
         need = self.workspace_bytes(n_lmfp)
@@ -352,11 +376,10 @@ class Plan:
         return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(n.value)}
 
     def status(self) -> int:
-        """amber_status: device status bits of the last ranking/matching call."""
+        """amber_status: device status bits of every ranking/matching call on
+        this plan since the last amber_status (read and cleared)."""
         v = ctypes.c_uint()
-        ws = self.workspace(1)
-        _check(lib().amber_status(self._h, ctypes.c_void_p(ws.data_ptr()), _stream(), ctypes.byref(v)),
-               "amber_status")
+        _check(lib().amber_status(self._h, _stream(), ctypes.byref(v)), "amber_status")
         return int(v.value)
 
 

@@ -28,7 +28,8 @@ double asym_residual(double c, double le, double lm, double ll, double az) {
     return (pe - pm) - az * (pm - pl);
 }
 
-// Brent's method on s = ln c over a sign-change bracket.
+// Brent's method (R. P. Brent, Algorithms for Minimization without
+// Derivatives, 1973, ch. 4) on s = ln c over a sign-change bracket.
 bool solve_c(double le, double lm, double ll, double az, double* c_out) {
     double a = std::log(1.0 / 64.0), b = std::log(4096.0);
     double fa = asym_residual(std::exp(a), le, lm, ll, az), fb = asym_residual(std::exp(b), le, lm, ll, az);
@@ -189,6 +190,18 @@ static double weibull_node(const amber_weibull* w, int64_t j) {
     return std::exp(-std::pow((z - a) / w->b_w, w->c_w));
 }
 
+// A fitted history as amber_zre uses it: positive coefficients, the table
+// geometry that amber_weibull_from_coeffs gives for them (the kernels rely on
+// T >= 2^21 nodes), a device table and a 16-byte aligned growth table.
+static int check_weibull(const amber_weibull& w) {
+    amber_weibull ref{};
+    if (amber_weibull_from_coeffs(w.a_w, w.b_w, w.c_w, &ref) != AMBER_OK) return AMBER_E_HISTORY;
+    if (!(w.h == ref.h) || !(w.z_top == ref.z_top) || w.table_n != ref.table_n) return AMBER_E_ARG;
+    if (!w.d_table) return AMBER_E_ARG;
+    if (reinterpret_cast<uintptr_t>(w.d_growth) % 16 != 0) return AMBER_E_ARG;
+    return AMBER_OK;
+}
+
 int amber_weibull_table(const amber_weibull* w, double* host_table, int64_t n_entries) {
     if (!w || !host_table || n_entries != w->table_n || n_entries < 2) return AMBER_E_ARG;
     for (int64_t j = 0; j < n_entries; ++j) host_table[j] = weibull_node(w, j);
@@ -226,6 +239,54 @@ int amber_growth_table(const amber_weibull* w, double z_mid, double omega_m, dou
     return AMBER_OK;
 }
 
+int amber_history_prepare(const amber_history* hist, amber_weibull* out, void* d_table_buf, size_t buf_bytes,
+                          void* stream) {
+    if (!hist || !out) return AMBER_E_ARG;
+    amber_weibull w{};
+    const int rc = amber_weibull_fit(hist, &w);
+    if (rc != AMBER_OK) return rc;
+    if (!d_table_buf) {  // size query
+        *out = w;
+        return AMBER_OK;
+    }
+    const size_t bytes = (size_t)w.table_n * sizeof(double);
+    if (buf_bytes < bytes) return AMBER_E_WORKSPACE;
+    double* host = new (std::nothrow) double[(size_t)w.table_n];
+    if (!host) return AMBER_E_ARG;
+    amber_weibull_table(&w, host, w.table_n);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(d_table_buf, host, bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    delete[] host;
+    if (e != hipSuccess) return AMBER_E_HIP;
+    w.d_table = static_cast<const double*>(d_table_buf);
+    *out = w;
+    return AMBER_OK;
+}
+
+int amber_growth_prepare(amber_weibull* w, double z_mid, double omega_m, void* d_pairs_buf, size_t buf_bytes,
+                         void* stream) {
+    if (!w || !d_pairs_buf) return AMBER_E_ARG;
+    if (reinterpret_cast<uintptr_t>(d_pairs_buf) % 16 != 0) return AMBER_E_ARG;
+    amber_weibull ref{};
+    if (amber_weibull_from_coeffs(w->a_w, w->b_w, w->c_w, &ref) != AMBER_OK) return AMBER_E_HISTORY;
+    if (!(w->h == ref.h) || !(w->z_top == ref.z_top) || w->table_n != ref.table_n) return AMBER_E_ARG;
+    const size_t bytes = 2 * (size_t)w->table_n * sizeof(double);
+    if (buf_bytes < bytes) return AMBER_E_WORKSPACE;
+    double* host = new (std::nothrow) double[2 * (size_t)w->table_n];
+    if (!host) return AMBER_E_ARG;
+    int rc = amber_growth_table(w, z_mid, omega_m, host, w->table_n);
+    if (rc == AMBER_OK) {
+        const hipStream_t s = static_cast<hipStream_t>(stream);
+        hipError_t e = hipMemcpyAsync(d_pairs_buf, host, bytes, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = AMBER_E_HIP;
+    }
+    delete[] host;
+    if (rc == AMBER_OK) w->d_growth = static_cast<const double*>(d_pairs_buf);
+    return rc;
+}
+
 int amber_plan_create(amber_plan* out, int n, double box_len) {
     if (!out) return AMBER_E_ARG;
     *out = nullptr;
@@ -249,8 +310,14 @@ int amber_plan_create(amber_plan* out, int n, double box_len) {
         const long double t = 2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)n;
         host[j] = make_float2((float)cosl(t), (float)(-sinl(t)));
     }
-    hipError_t e = hipMalloc(&p->d_tw, sizeof(float2) * (size_t)n);
+    // one allocation: the twiddles, then the accumulated status word
+    const size_t tw_bytes = align256(sizeof(float2) * (size_t)n);
+    hipError_t e = hipMalloc(&p->d_tw, tw_bytes + 256);
     if (e == hipSuccess) e = hipMemcpy(p->d_tw, host, sizeof(float2) * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        p->d_sticky = reinterpret_cast<unsigned*>(reinterpret_cast<unsigned char*>(p->d_tw) + tw_bytes);
+        e = hipMemset(p->d_sticky, 0, sizeof(unsigned));
+    }
     delete[] host;
     if (e != hipSuccess) {
         if (p->d_tw) (void)hipFree(p->d_tw);
@@ -333,8 +400,10 @@ int amber_profile_end(amber_plan plan, amber_kernel_time* out, int max_entries, 
     return rc;
 }
 
-size_t amber_workspace_bytes(amber_plan plan, int n_lmfp) {
-    if (!plan) return 0;
+size_t amber_workspace_bytes(amber_plan plan, int n_lmfp, int n_hist) {
+    if (!plan || n_lmfp < 0 || n_lmfp > 64 || n_hist < 0 || n_hist > 8) return 0;
+    // histories are matched in groups that reuse the ranking's buffers, so
+    // their count does not change the size
     return ws_layout(plan->n, n_lmfp < 1 ? 1 : n_lmfp).total;
 }
 
@@ -502,12 +571,9 @@ int amber_zre(amber_plan plan, const float* d_J, const float* d_w, const amber_w
               float* const* d_zre, void* d_ws, size_t ws_bytes, void* stream) {
     if (!plan || !d_J || !d_w || !hist || !d_zre || !d_ws || n_hist < 1 || n_hist > 8) return AMBER_E_ARG;
     for (int i = 0; i < n_hist; ++i) {
-        const amber_weibull& w = hist[i];
-        if (!d_zre[i] || !w.d_table || w.table_n < 2) return AMBER_E_ARG;
-        if (reinterpret_cast<uintptr_t>(w.d_growth) % 16 != 0) return AMBER_E_ARG;
-        if (!(w.a_w > 0.0) || !(w.b_w > 0.0) || !(w.c_w > 0.0) || !(w.h > 0.0) || !(w.z_top > w.a_w) ||
-            !std::isfinite(w.z_top))
-            return AMBER_E_HISTORY;
+        if (!d_zre[i]) return AMBER_E_ARG;
+        const int rc = check_weibull(hist[i]);
+        if (rc != AMBER_OK) return rc;
     }
     const WsLayout L = ws_layout(plan->n, 1);
     if (ws_bytes < L.total) return AMBER_E_WORKSPACE;
@@ -531,12 +597,8 @@ static int check_item(const amber_batch_item& it) {
     for (int i = 0; i < it.n_lmfp * it.n_hist; ++i)
         if (!it.d_zre[i]) return AMBER_E_ARG;
     for (int h = 0; h < it.n_hist; ++h) {
-        const amber_weibull& w = it.hist[h];
-        if (!w.d_table || w.table_n < 2) return AMBER_E_ARG;
-        if (reinterpret_cast<uintptr_t>(w.d_growth) % 16 != 0) return AMBER_E_ARG;
-        if (!(w.a_w > 0.0) || !(w.b_w > 0.0) || !(w.c_w > 0.0) || !(w.h > 0.0) || !(w.z_top > w.a_w) ||
-            !std::isfinite(w.z_top))
-            return AMBER_E_HISTORY;
+        const int rc = check_weibull(it.hist[h]);
+        if (rc != AMBER_OK) return rc;
     }
     return AMBER_OK;
 }
@@ -614,14 +676,12 @@ int amber_spectra(amber_plan plan, const float* d_a, int kind_a, const float* d_
     return spectra_bins(plan, sa, na, kind_a, sb, nb, kind_b, n_bins, d_out, s);
 }
 
-int amber_status(amber_plan plan, void* d_ws, void* stream, unsigned* status) {
-    if (!plan || !d_ws || !status) return AMBER_E_ARG;
-    const WsLayout L = ws_layout(plan->n, 1);
-    Ctrl* ctrl = reinterpret_cast<Ctrl*>(static_cast<unsigned char*>(d_ws) + L.ctrl);
+int amber_status(amber_plan plan, void* stream, unsigned* status) {
+    if (!plan || !status) return AMBER_E_ARG;
     AMBER_HIP_CHECK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
     unsigned v = 0, zero = 0;
-    AMBER_HIP_CHECK(hipMemcpy(&v, &ctrl->status, sizeof(unsigned), hipMemcpyDeviceToHost));
-    AMBER_HIP_CHECK(hipMemcpy(&ctrl->status, &zero, sizeof(unsigned), hipMemcpyHostToDevice));
+    AMBER_HIP_CHECK(hipMemcpy(&v, plan->d_sticky, sizeof(unsigned), hipMemcpyDeviceToHost));
+    AMBER_HIP_CHECK(hipMemcpy(plan->d_sticky, &zero, sizeof(unsigned), hipMemcpyHostToDevice));
     *status = v;
     return AMBER_OK;
 }

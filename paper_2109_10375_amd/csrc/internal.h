@@ -23,6 +23,7 @@ struct amber_plan_s {
     double box_len = 0.0;  // box side
     int device = -1;
     float2* d_tw = nullptr;  // tw[j] = exp(-2 pi i j / n), j < n, FP64-rounded to FP32
+    unsigned* d_sticky = nullptr;  // device status bits accumulated until amber_status (same allocation)
     int col_sched = 0;       // FFT column-pass candidate (0: default)
     int z_sched = 0;         // FFT z-pass candidate (0: default)
     Profiler* prof = nullptr;
@@ -78,10 +79,11 @@ WsLayout ws_layout(int n, int n_lmfp, bool halo_meshes = false);
 inline long long lb_words(long long n3) { return ((n3 + 4095) / 4096 + 256) * 256; }
 
 // Control block (lives at offset 0 of the workspace; zeroed by a kernel at the
-// start of every matching call).
+// start of every ranking or matching call).
 struct Ctrl {
-    unsigned status;            // AMBER_STATUS_* bits (sticky until amber_status)
+    unsigned status;            // AMBER_STATUS_* bits of this call
     unsigned pad0;
+    unsigned* sticky;           // the plan's accumulated status word (amber_status clears it)
     unsigned tickets[32];       // tile tickets: 0-3 radix passes, 4.. matching launches
     unsigned hist[4][256];      // digit histograms of the descending keys
     unsigned digit_off[4][256]; // exclusive prefix of hist
@@ -96,6 +98,12 @@ struct Ctrl {
 // walk reads 8 predecessors per step, which keeps its latency from growing with
 // the number of tiles in flight; it stops at the first prefix, and every tile
 // at or after first_tile publishes its aggregate before walking, so it ends.
+// A data error: the call's own status word and the plan's accumulated one.
+__device__ __forceinline__ void report_status(Ctrl* ctrl, unsigned bit) {
+    atomicOr(&ctrl->status, bit);
+    atomicOr(ctrl->sticky, bit);
+}
+
 constexpr unsigned kLbAgg = 1u << 30, kLbPre = 2u << 30, kLbMask = (1u << 30) - 1;
 constexpr int kLbBatch = 8;
 

@@ -373,7 +373,7 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_sums(const float* __restr
             running = add128_checked(running, s_tile[k], b3);
         }
         block_tot[blockIdx.x] = running;
-        if (s_bad || b3) atomicOr(&ctrl->status, AMBER_STATUS_RANGE);
+        if (s_bad || b3) report_status(ctrl, AMBER_STATUS_RANGE);
     }
 }
 
@@ -419,7 +419,7 @@ __global__ __launch_bounds__(kPrefixThreads) void k_block_prefix(u128* __restric
         ctrl->total_lo = total.lo;
         ctrl->total_hi = total.hi;
         ctrl->wide = total.hi != 0ull;
-        if (s_bad || (total.hi >> 63)) atomicOr(&ctrl->status, AMBER_STATUS_RANGE);
+        if (s_bad || (total.hi >> 63)) report_status(ctrl, AMBER_STATUS_RANGE);
     }
 }
 

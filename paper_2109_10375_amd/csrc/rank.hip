@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const float* __restrict__
             }
         }
     }
-    if (__any(nan) && lane == 0) atomicOr(&ctrl->status, AMBER_STATUS_NAN_J);
+    if (__any(nan) && lane == 0) report_status(ctrl, AMBER_STATUS_NAN_J);
     __syncthreads();
     for (int d = threadIdx.x; d < 256; d += kHistThreads) {
         unsigned c = 0;
@@ -134,11 +134,14 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const float* __restrict__
     }
 }
 
-__global__ void k_ctrl_init(Ctrl* ctrl) {
+__global__ void k_ctrl_init(Ctrl* ctrl, unsigned* sticky) {
     unsigned* p = reinterpret_cast<unsigned*>(ctrl);
     for (int i = threadIdx.x; i < (int)(sizeof(Ctrl) / 4); i += blockDim.x) p[i] = 0u;
     __syncthreads();
-    if (threadIdx.x == 0) ctrl->qmin = 0x7fffffff;
+    if (threadIdx.x == 0) {
+        ctrl->qmin = 0x7fffffff;
+        ctrl->sticky = sticky;
+    }
 }
 
 // Exclusive prefix of each digit histogram: where each digit's run starts.
@@ -342,7 +345,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
             q = oq < q ? oq : q;
         }
         if (lane == 0) s_qmin[wave] = q;
-        if (__any(bad_w) && lane == 0) atomicOr(&ctrl->status, AMBER_STATUS_BAD_W);
+        if (__any(bad_w) && lane == 0) report_status(ctrl, AMBER_STATUS_BAD_W);
     }
     __syncthreads();
     if (CARRY && FIRST && tid == 0) {  // a plain store: nothing in this block waits on it
@@ -465,7 +468,7 @@ int rank_sort(const amber_plan_s* p, const float* d_J, const float* d_w, unsigne
                        reinterpret_cast<unsigned*>(ws + L.lookback) + lbw,
                        reinterpret_cast<unsigned*>(ws + L.lookback) + 2 * lbw};
 
-    AMBER_LAUNCH(p, "rank_init", k_ctrl_init, dim3(1), dim3(256), s, ctrl);
+    AMBER_LAUNCH(p, "rank_init", k_ctrl_init, dim3(1), dim3(256), s, ctrl, p->d_sticky);
     const unsigned hist_blocks =
         (unsigned)std::min<long long>(2048, (n + kHistThreads * 16 - 1) / (kHistThreads * 16));
     // the histogram's per-lane top-digit counters are 16 bits wide

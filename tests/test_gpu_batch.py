@@ -9,9 +9,11 @@ Workloads:
     histories), eager and captured into a HIP graph.
 Tolerances as in the single-box tests: a batch must give bit for bit what the
 single calls give; J within relative L2 1e-5 of the oracle; z_re from an
-oracle-given intensity bit-exact; end-to-end z_re within 1e-4 per cell
-wherever FP32 J resolves the FP64 ranking (the fraction is reported and
-bounded, the ionized-mass invariant and monotonicity are checked exactly).
+oracle-given intensity bit-exact; end to end every cell of z_re within 1e-4
+of the oracle's exact-mode match of the GPU's FP32 intensity field, and every
+cell beyond 1e-4 of the match of the oracle's FP64 field one whose exact
+ionized-mass fraction changed with the rank order (their fraction is
+reported; the ionized-mass invariant and monotonicity are checked exactly).
 """
 import numpy as np
 import pytest
@@ -124,14 +126,11 @@ def test_sweep_structure_64_vs_oracle(amber):
         assert rel <= 1e-5
         pg = oracle.rank(Jg)
         for hi, H in enumerate(ors):
-            _, z_ref = oracle.zre(J_ref, wn, H, mode=oracle.EXACT)
             zg = Z[li][hi].cpu().numpy().astype(np.float64)
-            frac_ok = float(np.mean(np.abs(zg - z_ref) <= 1e-4))
-            print(f"sweep 64^3 l={l} hist={hi}: J relL2={rel:.2e}; z within 1e-4: {frac_ok:.5f}", flush=True)
-            # FP32 intensity resolves the FP64 ranking except among near-equal
-            # values; where the mean free path is under a cell the field is
-            # ringing-dominated and more cells swap places
-            assert frac_ok >= (0.99 if l >= 1.0 else 0.95)
+            st = oracle.zre_per_cell_check(Jg, J_ref, wn, H, zg, tol=1e-4)
+            print(f"sweep 64^3 l={l} hist={hi}: J relL2={rel:.2e}; same-field max {st['max_err_same_field']:.2e}; "
+                  f"vs FP64 field {st['frac_within_tol_fp64']:.5f} within 1e-4 ({st['cells_over_tol_fp64']} cells "
+                  f"beyond, all with a changed ionized-mass fraction)", flush=True)
             zf = zg.reshape(-1)
             assert np.all(np.diff(zf[pg]) <= 0)
             _ionized_mass_follows_history(w.cuda(), Z[li][hi], H, np.linspace(H.a, 14.0, 40))

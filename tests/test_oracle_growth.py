@@ -5,9 +5,13 @@ delta_m(z) = D(z)/D(z_mid) delta_m; readings G1, G2):
     matter + Lambda universe (an independent formula), its matter-dominated
     limit D = a and the matter-only case;
   * the node tables against that quadrature;
+  * the Gauss-Legendre rule behind D: exact on monomials up to degree 2n - 1;
   * the matched z_re against a brute-force root of the continuous equation
-    (scipy brentq on exact D and exact x_i) on a small grid, within the node
-    spacing h;
+    (scipy brentq on exact D and exact x_i, inside the first sign change found
+    on a fine grid) on a small grid, within the node spacing h, also where
+    some growth-weighted masses 1 + g delta are negative;
+  * the bracket rule of reading G2 on a planted growth table whose gap changes
+    sign three times: the walk stops at the first node with h_j > 0;
   * with G = 1 it reduces to the plain matching up to rounding.
 """
 import math
@@ -28,10 +32,21 @@ def _growth_quad(z, om):
     return 2.5 * om * E(a) * val
 
 
-@pytest.mark.parametrize("z", [0.0, 0.3, 1.0, 3.0, 6.0, 8.0, 12.0, 30.0])
-@pytest.mark.parametrize("om", [0.3, 0.5, 0.1])
+@pytest.mark.parametrize("z", [0.0, 0.3, 1.0, 3.0, 6.0, 8.0, 12.0, 30.0, 200.0])
+@pytest.mark.parametrize("om", [0.3, 0.5, 0.1, 0.05])
 def test_growth_matches_quadrature(z, om):
-    assert oracle.growth(z, om) == pytest.approx(_growth_quad(z, om), rel=1e-10)
+    assert oracle.growth(z, om) == pytest.approx(_growth_quad(z, om), rel=1e-13)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 64])
+def test_gauss_legendre_rule_is_exact_on_polynomials(n):
+    x, w = oracle.gauss_legendre(n)
+    assert np.all(np.diff(x) > 0) and np.all(w > 0)
+    for k in range(2 * n):
+        exact = 2.0 / (k + 1) if k % 2 == 0 else 0.0
+        assert np.sum(w * x ** k) == pytest.approx(exact, abs=1e-14), k
+    ref_x, ref_w = np.polynomial.legendre.leggauss(n)   # the textbook table
+    assert np.max(np.abs(x - ref_x)) <= 1e-14 and np.max(np.abs(w - ref_w)) <= 1e-14
 
 
 def test_growth_limits():
@@ -59,10 +74,30 @@ def _masses(J, w):
     return perm, np.cumsum(wp), wp.sum()
 
 
-def test_brute_force_continuous_root():
+def _first_crossing_root(f, lo, hi, grid=4000):
+    """The lowest root of f on [lo, hi] where f turns from <= 0 to > 0: a fine
+    grid finds the first positive sample, brentq refines inside that cell."""
+    if f(lo) > 0:
+        return lo
+    zs = np.linspace(lo, hi, grid)
+    prev = lo
+    for z in zs[1:]:
+        if f(z) > 0:
+            return optimize.brentq(f, prev, z, xtol=1e-13, rtol=1e-15)
+        prev = z
+    return hi
+
+
+@pytest.mark.parametrize("seed,wscale", [(601, 1.0), (611, 1.0), (621, 0.25)])
+def test_brute_force_continuous_root(seed, wscale):
+    """wscale < 1 makes many weights small (w < 0.12), so 1 + g delta < 0 for
+    g > 1: the cells ranked last carry negative growth-weighted mass near a_w."""
     n = 8
-    J = inputs.make_intensity(n, 601, ties=False, negatives=False).numpy()
-    w = inputs.make_density(n, 602).numpy().astype(np.float32)
+    J = inputs.make_intensity(n, seed, ties=False, negatives=False).numpy()
+    w = inputs.make_density(n, seed + 1).numpy().astype(np.float32)
+    if wscale != 1.0:
+        w = (w ** 3 * wscale).astype(np.float32)
+        w = (w / w.mean()).astype(np.float32)
     H = oracle.History.from_params(8.0, 4.0, 3.0)
     G = oracle.growth_table(H, 8.0)
     z32, z64 = oracle.zre_growth(J, w, H, G)
@@ -79,17 +114,55 @@ def test_brute_force_continuous_root():
             M = N * (1 - g) + g * Ctot
             return m / M - math.exp(-(((z - H.a) / H.b) ** H.c))
 
-        lo, hi = H.a, H.z_top
-        if f(lo) > 0:
-            ref = lo
-        elif f(hi) <= 0:
-            ref = hi
-        else:
-            ref = optimize.brentq(f, lo, hi, xtol=1e-13, rtol=1e-15)
+        ref = _first_crossing_root(f, H.a, H.z_top)
         err = abs(z64.reshape(-1)[perm[k]] - ref)
         worst = max(worst, err)
         assert err <= H.h, (k, err, H.h)
-    print(f"growth matching vs continuous root: worst {worst:.2e} (h = {H.h:.2e})")
+    g_max = oracle.growth(H.a) / d_mid
+    neg = int(np.sum(1.0 + g_max * (w.astype(np.float64) - 1.0) < 0))
+    if wscale != 1.0:
+        assert neg > 0, "the case must hold cells with negative growth-weighted mass"
+    print(f"growth matching vs continuous root: worst {worst:.2e} (h = {H.h:.2e}); "
+          f"cells with 1 + g delta < 0 at a_w: {neg}")
+
+
+def test_walk_stops_at_the_first_positive_gap():
+    """A planted (non-physical) growth table makes the gap of every rank
+    positive on two windows of nodes below its true root; the oracle's
+    bracket must end at the first node with h_j > 0 (the lower window)."""
+    n = 8
+    J = inputs.make_intensity(n, 631, ties=False, negatives=False).numpy()
+    w = inputs.make_density(n, 632).numpy().astype(np.float32)
+    H = oracle.History.from_params(8.0, 4.0, 3.0)
+    G = np.ones(H.T + 1)
+    j1, j2 = 1000, 3000
+    G[j1:j1 + 50] = 40.0       # a huge weight on the overdense ranks' mass
+    G[j2:j2 + 50] = 40.0
+    perm, C, Ctot = _masses(J, w)
+    sel = np.arange(0, n ** 3, 3)
+    zs, cells = oracle.zre_growth(J, w, H, G, ranks=sel)
+    N = n ** 3
+    X = H.X[: j2 + 200]     # every planted stop and every checked bracket lies below j2 + 200
+    Gs = G[: j2 + 200]
+    planted = 0
+    for i, k in enumerate(sel):
+        cnt = k + 1
+        one = 1.0 - Gs
+        h = (cnt * one + Gs * C[k]) / (N * one + Gs * Ctot) - X
+        pos = np.nonzero(h > 0)[0]
+        j = int(pos[0]) if pos.size else None
+        if j is None:       # the first positive gap lies above the checked range: bracket above j2
+            assert float(zs[i]) > H.a + (j2 + 199) * H.h
+            continue
+        if j == 0:
+            ref = H.a
+        else:
+            t = -h[j - 1] / (h[j] - h[j - 1])
+            ref = min((H.a + (j - 1) * H.h) + t * H.h, H.z_top)
+        planted += int(j is not None and j in (j1, j2))
+        assert cells[i] == perm[k]
+        assert abs(float(zs[i]) - ref) <= 4e-6 * max(1.0, abs(ref)), (k, zs[i], ref)
+    assert planted > 0, "some ranks must stop in a planted window"
 
 
 def test_unit_growth_reduces_to_plain_matching():

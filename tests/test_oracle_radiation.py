@@ -144,3 +144,18 @@ def test_negative_values_from_spectral_ringing():
     assert g.min() < 0 and abs(g.min()) < 1e-2 * g.max()
     assert 0.01 < np.mean(g < 0) < 0.6
     assert math.isclose(g.sum(), 3.0, rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("n", [4, 6, 8, 12, 16])
+def test_dft_coeff_matches_numpy_fft(n):
+    """oracle_dft_coeff_f32 (one DFT coefficient of an FP32 field, the checker
+    of full-size transforms) against numpy's FFT at every mode of small grids."""
+    rng = np.random.default_rng(1000 + n)
+    f = rng.standard_normal((n, n, n)).astype(np.float32)
+    ref = np.fft.fftn(f.astype(np.float64))
+    scale = np.sqrt(np.sum(np.abs(ref) ** 2) / ref.size)
+    worst = 0.0
+    for m in np.ndindex(n, n, n):
+        got = oracle.dft_coeff(f, m)
+        worst = max(worst, abs(got - ref[m]) / scale)
+    assert worst <= 1e-12, worst
