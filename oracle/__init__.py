@@ -18,7 +18,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "amber_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# AMBER_ORACLE_LIB selects another build of the same source (the sanitizer run)
+_LIB = os.environ.get("AMBER_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 OK = 0
 E_ARG = -1
