@@ -79,6 +79,19 @@ def algorithmic_bytes(n: int) -> dict:
     }
 
 
+# The survey's pass model of the 1024^3 pipeline (bytes per cell): FFT 5 passes of
+# 8 B (3 forward + 3 inverse transforms with the x pair fused) = 40; radix sort:
+# histogram 4 + digit passes 12 + 16 + 16 + 12 = 60 (key and index only); matching:
+# rank order 4 + weight 4 + z_re 4 = 12.  The matching stage's 12 B are split
+# here over its first and last kernels.  Nyquist-plane launches are part of
+# their passes' bytes.
+PASS_MODEL_BYTES_PER_CELL = {
+    "fft_z_r2c": 8, "fft_y": 8, "fft_x_mul": 8, "fft_y_inv": 8, "fft_z_c2r": 8,
+    "rank_hist": 4, "rank_pass0": 12, "rank_pass1": 16, "rank_pass2": 16, "rank_pass3": 12,
+    "match_scan_partition": 8, "match_leaf_scatter": 4,
+}
+STAGES = (("fft", "fft_", 40), ("sort", "rank_", 60), ("match", "match_", 12))
+
 KERNEL_SOURCES = {"fft_": "fft.hip", "rank_": "rank.hip", "match_": "match.hip"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_box1024.txt")
 
@@ -580,11 +593,38 @@ def main() -> int:
     for tot_ms, name, launches, avg, b, gbs in rows:
         log(f"[bench] {name:22s} {launches:8d} {avg:9.3f} {100 * tot_ms / tot_all:5.1f}% "
             f"{(b or 0) / 1e9:8.2f} {gbs or 0:8.0f} {100 * (gbs or 0) / HBM_PEAK_GBS:5.1f}")
-    dom = next(r for r in rows if r[4])
+    # the dominant kernel (largest share of the step) against the survey's pass-model bytes
+    dom = next(r for r in rows if r[1] in PASS_MODEL_BYTES_PER_CELL)
+    pm_bytes = PASS_MODEL_BYTES_PER_CELL[dom[1]] * n3
+    pm_gbs = pm_bytes / (dom[3] * 1e-3) / 1e9
     traffic, traffic_src = measured_traffic(dom[1], n)
-    roof = {"bound": "hbm", "kernel": dom[1], "achieved": round(dom[5], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(dom[5] / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": traffic_src,
-            "algorithmic_bytes_per_launch": dom[4], "avg_launch_ms": round(dom[3], 4)}
+    roof = {"bound": "hbm", "kernel": dom[1], "achieved": round(pm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(pm_gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": traffic_src,
+            "bytes_model": "survey pass model (FFT 40, sort 60, matching 12 B per cell)",
+            "algorithmic_bytes_per_launch": pm_bytes, "avg_launch_ms": round(dom[3], 4),
+            "design_bytes_per_launch": dom[4],
+            "design_frac": round((dom[5] or 0) / HBM_PEAK_GBS, 4)}
+    stages = {}
+    step_ms = 1e3 * elapsed / args.steps
+    for stage, prefix, model_b in STAGES:
+        ks = [r for r in rows if r[1].startswith(prefix)]
+        ms = sum(r[0] for r in ks) / args.steps
+        design_b = sum(alg.get(r[1], 0) * r[2] for r in ks) / args.steps
+        kc = [r for r in ks if r[1] in alg]
+        counted = [measured_traffic(r[1], n)[0] for r in kc]
+        counter_b = (sum(c * r[2] for c, r in zip(counted, kc)) / args.steps
+                     if kc and all(c is not None for c in counted) else None)
+        gbs = model_b * n3 / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        stages[stage] = {"ms_per_step": round(ms, 3), "share": round(ms / step_ms, 4),
+                         "pass_model_bytes_per_cell": model_b, "pass_model_gbs": round(gbs, 1),
+                         "pass_model_frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "design_bytes_per_cell": round(design_b / n3, 2),
+                         "design_frac": round(design_b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else 0.0,
+                         "counter_bytes_per_cell": round(counter_b / n3, 2) if counter_b is not None else None,
+                         "kernels": [r[1] for r in ks]}
+        log(f"[bench] stage {stage:5s}: {ms:7.3f} ms/step, pass model {model_b} B/cell -> {gbs:7.0f} GB/s "
+            f"({100 * gbs / HBM_PEAK_GBS:4.1f}% of HBM); design {design_b / n3:5.1f} B/cell; counters "
+            f"{'n/a' if counter_b is None else f'{counter_b / n3:5.1f} B/cell'}")
     pipe_bytes = sum(alg[r[1]] * r[2] for r in rows if r[1] in alg) / args.steps
     out = {
         "metric": "grid cells/s (radiation FFT-convolve + zre match) at 1024^3; p50/p99 box latency",
@@ -614,6 +654,7 @@ def main() -> int:
         "copy_peak_gbs": round(copy_gbs, 1),
         "pass_model_frac_copy": round(112 * n3 / (elapsed / args.steps) / 1e9 / copy_gbs, 4),
         "roofline": roof,
+        "stages": stages,
         "kernels_ms_per_step": {r[1]: round(r[0] / args.steps, 4) for r in rows},
     }
     del J, z, w, S
