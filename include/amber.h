@@ -268,6 +268,22 @@ int amber_zre(amber_plan plan, const float* d_J, const float* d_w,
               const amber_weibull* hist, int n_hist, float* const* d_zre,
               void* d_ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): amber_zre
+ * without a workspace.  Its scratch is a static device array of
+ * AMBER_NOALLOC_SCRATCH_BYTES (68 MiB) in the library, one copy per device,
+ * held until the process ends; it suffices for plans of N <= AMBER_NOALLOC_MAX_N
+ * (128).  Arguments and results as amber_zre (bit-identical z_re).  The call
+ * allocates nothing and enqueues only kernels.  Every call on a device shares
+ * that device's array, which keeps the last call's contents: calls that
+ * overlap in time on one device race and must be ordered by the caller.
+ * AMBER_E_SIZE for a plan with N > AMBER_NOALLOC_MAX_N; AMBER_E_HIP when the
+ * array's device address could not be looked up at plan creation. */
+#define AMBER_NOALLOC_MAX_N 128
+#define AMBER_NOALLOC_SCRATCH_BYTES (68u << 20)
+int amber_zre_noalloc(amber_plan plan, const float* d_J, const float* d_w, const amber_weibull* hist, int n_hist,
+                      float* const* d_zre, void* stream);
+
 /* Waits for `stream`, then returns in *status and clears the device status
  * bits (AMBER_STATUS_*) of every ranking and matching call on this plan since
  * the plan was created or amber_status last cleared them, whatever workspace

@@ -26,8 +26,10 @@ SYMBOLS = [
     "amber_profile_end", "amber_batch_workspace_bytes", "amber_batch_run", "amber_spectra_workspace_bytes",
     "amber_spectra", "amber_growth_table", "amber_halo_workspace_bytes", "amber_radiation_from_halos",
     "amber_fft_schedules", "amber_fft_schedule_info", "amber_plan_set_schedule", "amber_plan_get_schedule",
-    "amber_plan_tune", "amber_history_prepare", "amber_growth_prepare",
+    "amber_plan_tune", "amber_history_prepare", "amber_growth_prepare", "amber_zre_noalloc",
 ]
+NOALLOC_MAX_N = 128
+NOALLOC_SCRATCH_BYTES = 68 << 20
 ASSIGN_NGP, ASSIGN_CIC, ASSIGN_TSC = 1, 2, 3
 FIELD_RAW, FIELD_OVERDENSITY, FIELD_REDSHIFT = 0, 1, 2
 
@@ -96,6 +98,7 @@ def lib() -> ctypes.CDLL:
         L.amber_radiation.argtypes = [vp, vp, ctypes.POINTER(d), i, ctypes.POINTER(vp), vp, sz, vp]
         L.amber_rank.argtypes = [vp, vp, vp, vp, sz, vp]
         L.amber_zre.argtypes = [vp, vp, vp, ctypes.POINTER(AmberWeibull), i, ctypes.POINTER(vp), vp, sz, vp]
+        L.amber_zre_noalloc.argtypes = [vp, vp, vp, ctypes.POINTER(AmberWeibull), i, ctypes.POINTER(vp), vp]
         L.amber_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_uint)]
         L.amber_history_prepare.argtypes = [ctypes.POINTER(AmberHistory), ctypes.POINTER(AmberWeibull), vp, sz, vp]
         L.amber_growth_prepare.argtypes = [ctypes.POINTER(AmberWeibull), d, d, vp, sz, vp]
@@ -317,6 +320,20 @@ class Plan:
         _check(lib().amber_zre(self._h, _dev_ptr(J, torch.float32, self.n3, "J"),
                                _dev_ptr(w, torch.float32, self.n3, "w"), harr, len(hists), ptrs,
                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "amber_zre")
+        return list(out)
+
+    def zre_noalloc(self, J: torch.Tensor, w: torch.Tensor, hists: Sequence[History],
+                    out: Sequence[torch.Tensor] | None = None):
+        """amber_zre_noalloc: amber_zre with the library's static scratch
+        instead of a workspace (N <= 128; nothing is allocated when out is
+        given)."""
+        if out is None:
+            out = [torch.empty((self.n,) * 3, dtype=torch.float32, device=self.device) for _ in hists]
+        harr = (AmberWeibull * len(hists))(*[h.w for h in hists])
+        ptrs = (ctypes.c_void_p * len(hists))(*[_dev_ptr(o, torch.float32, self.n3, "z_re").value for o in out])
+        _check(lib().amber_zre_noalloc(self._h, _dev_ptr(J, torch.float32, self.n3, "J"),
+                                       _dev_ptr(w, torch.float32, self.n3, "w"), harr, len(hists), ptrs, _stream()),
+               "amber_zre_noalloc")
         return list(out)
 
     def spectra(self, a: torch.Tensor, b: torch.Tensor | None = None, kind_a: int = FIELD_RAW,

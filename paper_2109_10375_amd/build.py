@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libamber.so")
-SOURCES = ["amber_api.cpp", "fft.hip", "rank.hip", "match.hip", "spectra.hip", "halos.hip"]
+SOURCES = ["amber_api.cpp", "fft.hip", "rank.hip", "match.hip", "spectra.hip", "halos.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -324,6 +324,9 @@ int amber_plan_create(amber_plan* out, int n, double box_len) {
         delete p;
         return AMBER_E_HIP;
     }
+    // the no-allocation matching call's scratch on this device (a failed
+    // lookup leaves it NULL: that call then reports AMBER_E_HIP)
+    if (n <= AMBER_NOALLOC_MAX_N) (void)noalloc_scratch_address(p->device, &p->d_scratch);
     *out = p;
     return AMBER_OK;
 }

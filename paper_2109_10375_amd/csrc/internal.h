@@ -24,6 +24,7 @@ struct amber_plan_s {
     int device = -1;
     float2* d_tw = nullptr;  // tw[j] = exp(-2 pi i j / n), j < n, FP64-rounded to FP32
     unsigned* d_sticky = nullptr;  // device status bits accumulated until amber_status (same allocation)
+    void* d_scratch = nullptr;     // this device's copy of the static scratch of amber_zre_noalloc
     int col_sched = 0;       // FFT column-pass candidate (0: default)
     int z_sched = 0;         // FFT z-pass candidate (0: default)
     Profiler* prof = nullptr;
@@ -73,6 +74,10 @@ struct WsLayout {
 };
 
 WsLayout ws_layout(int n, int n_lmfp, bool halo_meshes = false);
+
+// Device address of the static scratch array of amber_zre_noalloc on `device`
+// (noalloc.hip), looked up once per device with that device current.
+int noalloc_scratch_address(int device, void** out);
 
 // Words in each look-back region: 256 per 4096-cell tile, plus 256 tiles of
 // slack for partitions whose tiles do not straddle buckets.

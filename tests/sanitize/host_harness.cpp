@@ -86,7 +86,11 @@ int main() {
                 if (nl > 1) EXPECT(L.spec_b >= L.nyq_a + (size_t)n * n * 8);
                 if (halo) EXPECT(L.mesh[1] + n3 * 4 <= L.bins && L.halo_tab + (size_t)n * 32 <= L.total);
             }
-    std::printf("layouts: %zu sizes\n", sizeof(sizes) / sizeof(sizes[0]));
+    // the no-allocation matching call's static scratch holds the workspace of its largest grid
+    EXPECT(ws_layout(AMBER_NOALLOC_MAX_N, 1).total <= (size_t)AMBER_NOALLOC_SCRATCH_BYTES);
+    std::printf("layouts: %zu sizes; no-allocation scratch %zu of %zu bytes used at N = %d\n",
+                sizeof(sizes) / sizeof(sizes[0]), ws_layout(AMBER_NOALLOC_MAX_N, 1).total,
+                (size_t)AMBER_NOALLOC_SCRATCH_BYTES, AMBER_NOALLOC_MAX_N);
 
     // 5. compute calls reject bad arguments on the host, before any device work
     float* dummy = reinterpret_cast<float*>(X.data());

@@ -21,3 +21,7 @@ int match_scan(const amber_plan_s*, const amber_weibull*, int, float* const*, un
 int status_collect(const amber_plan_s*, unsigned char*, const WsLayout&, unsigned*, bool, hipStream_t) {
     return AMBER_E_UNIMPL;
 }
+int noalloc_scratch_address(int, void** out) {
+    *out = nullptr;
+    return AMBER_E_HIP;
+}
