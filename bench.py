@@ -321,16 +321,25 @@ def bench_mixed(args) -> dict:
     batch = amber.Batch(items)
     cells = sum(c.n ** 3 for c in cfgs)
     el_e, ms_e = _time_steps(batch.run, args.steps, args.warmup)
-    g = torch.cuda.CUDAGraph()
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        with torch.cuda.graph(g, stream=side):
-            batch.run()
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    el_g, ms_g = _time_steps(g.replay, args.steps, args.warmup)
-    if int(batch.status.sum()) != 0:
+
+    def capture(b):
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                b.run()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        return g
+
+    g1 = capture(batch)
+    el_g1, ms_g1 = _time_steps(g1.replay, args.steps, args.warmup)
+    lanes = amber.Batch(items, lanes=args.lanes)
+    el_l, ms_l = _time_steps(lanes.run, args.steps, args.warmup)
+    gl = capture(lanes)
+    el_g, ms_g = _time_steps(gl.replay, args.steps, args.warmup)
+    if int(batch.status.sum()) != 0 or int(lanes.status.sum()) != 0:
         raise RuntimeError("device status set")
 
     def serial():
@@ -342,10 +351,14 @@ def bench_mixed(args) -> dict:
     return _common(args, "grid cells/s over a mixed batch of 64 boxes (HIP graph replay)",
                    args.steps * cells / el_g, 1e3 * el_g / args.steps, WORKLOADS["c4"]["desc"],
                    {"cells_per_step": cells, "sizes": sorted(collections.Counter(c.n for c in cfgs).items()),
+                    "lanes": lanes.lanes,
                     "p50_ms": round(_pct(ms_g, 50), 3), "p99_ms": round(_pct(ms_g, 99), 3),
-                    "eager_batch": {"value": args.steps * cells / el_e, "ms_per_step": 1e3 * el_e / args.steps},
+                    "eager_batch_lanes": {"value": args.steps * cells / el_l, "ms_per_step": 1e3 * el_l / args.steps},
+                    "graph_one_lane": {"value": args.steps * cells / el_g1, "ms_per_step": 1e3 * el_g1 / args.steps},
+                    "eager_batch_one_lane": {"value": args.steps * cells / el_e, "ms_per_step": 1e3 * el_e / args.steps},
                     "serial_single_calls": {"value": args.steps * cells / el_s,
                                             "ms_per_step": 1e3 * el_s / args.steps},
+                    "speedup_vs_serial": round(el_s / el_g, 3),
                     "fft_schedule": scheds})
 
 
@@ -442,7 +455,17 @@ def bench_serving(args) -> dict:
     offered = sum(r.n ** 3 for r in reqs) / args.serve_seconds
     log(f"[bench] serving {len(reqs)} requests ({offered / 1e9:.2f} G cells/s offered)")
     st = server.serve(reqs)
-    # the same requests one at a time on one stream (no batching, no overlap), device time only
+    log(f"[bench] served: {st['requests']} requests in {st['batches']} batches ({st['requests_merged']} merged), "
+        f"p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms")
+    # the plain single-box path on the same arrivals: one request at a time, in arrival order
+    hists = server.hists
+    server = None                      # its per-slot workspaces
+    torch.cuda.empty_cache()
+    fifo = serve.Server(boxes, hbm_budget_bytes=args.hbm_budget_gb * 2 ** 30, max_batch=1, slots=1, merge=False)
+    fifo.hists = hists
+    sf = fifo.serve(reqs)
+    log(f"[bench] one at a time: p50 {sf['p50_ms']:.1f} ms, p99 {sf['p99_ms']:.1f} ms")
+    # the same requests back to back on one stream, device time only (no arrivals, no queueing)
     outs = {n: (torch.empty((n, n, n), dtype=torch.float32, device=dev),
                 torch.empty((n, n, n), dtype=torch.float32, device=dev)) for n in boxes}
     serial_ms = []
@@ -454,25 +477,31 @@ def bench_serving(args) -> dict:
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         b.plan.radiation(b.S, [r.l_mfp], out=[J])
-        b.plan.zre(J, b.w, [server.history(r.history)], out=[z])
+        b.plan.zre(J, b.w, [fifo.history(r.history)], out=[z])
         e1.record()
         serial_ms.append((e0, e1))
     torch.cuda.synchronize()
     serial_el = time.perf_counter() - t0
     serial_lat = sorted(a.elapsed_time(b_) for a, b_ in serial_ms)
     del outs
-    log(f"[bench] serial: {len(reqs)} requests in {serial_el:.2f} s")
+    log(f"[bench] back to back: {len(reqs)} requests in {serial_el:.2f} s")
     return _common(args, "served grid cells/s (Poisson requests, p50/p99 latency)", st["cells_per_s_busy"],
                    1e3 * st["busy_s"] / max(1, st["batches"]), WORKLOADS["c5"]["desc"],
                    {"p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
                     "mean_latency_ms": round(st["mean_ms"], 3), "requests": st["requests"],
-                    "batches": st["batches"], "offered_cells_per_s": offered,
+                    "batches": st["batches"], "requests_merged": st["requests_merged"],
+                    "p50_ms_by_n": st["p50_ms_by_n"], "p99_ms_by_n": st["p99_ms_by_n"],
+                    "offered_cells_per_s": offered,
                     "makespan_s": round(st["makespan_s"], 3), "busy_s": round(st["busy_s"], 3),
                     "slots": st["slots"], "max_batches_in_flight": st["max_batches_in_flight"],
                     "hbm_budget_gb": args.hbm_budget_gb, "arrivals_s": args.serve_seconds,
-                    "serial_single_calls": {"value": st["cells"] / serial_el, "seconds": round(serial_el, 3),
-                                            "p50_ms": round(_pct(serial_lat, 50), 3),
-                                            "p99_ms": round(_pct(serial_lat, 99), 3)},
+                    "single_box_path_same_arrivals": {
+                        "value": sf["cells_per_s_busy"], "p50_ms": round(sf["p50_ms"], 3),
+                        "p99_ms": round(sf["p99_ms"], 3), "mean_latency_ms": round(sf["mean_ms"], 3),
+                        "p99_ms_by_n": sf["p99_ms_by_n"], "busy_s": round(sf["busy_s"], 3)},
+                    "serial_back_to_back": {"value": st["cells"] / serial_el, "seconds": round(serial_el, 3),
+                                            "device_p50_ms": round(_pct(serial_lat, 50), 3),
+                                            "device_p99_ms": round(_pct(serial_lat, 99), 3)},
                     "fft_schedule": scheds})
 
 
@@ -488,6 +517,7 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="c5: seconds of Poisson arrivals")
     ap.add_argument("--hbm-budget-gb", type=int, default=96, help="c5: HBM for outputs of requests in flight")
     ap.add_argument("--serve-slots", type=int, default=2, help="c5: streams with batches in flight at once")
+    ap.add_argument("--lanes", type=int, default=4, help="c4: concurrent streams the batch's boxes are dealt to")
     ap.add_argument("--no-tune", action="store_true", help="keep the default FFT schedule (no autotuning)")
     ap.add_argument("--tune-reps", type=int, default=5, help="timed radiation passes per schedule pair and round")
     ap.add_argument("--tune-cache", default=None, metavar="JSON",

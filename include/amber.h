@@ -334,22 +334,44 @@ typedef struct {
     int n_hist;                  /* 1..8                                                   */
     const amber_weibull* hist;   /* host array of n_hist fitted histories (device tables)  */
     float* const* d_zre;         /* host array of n_lmfp * n_hist device pointers, entry
-                                    l * n_hist + h is z_re of J_l under history h          */
+                                    l * n_hist + h is z_re of J_l under history h, or NULL
+                                    when that pair is not wanted                           */
 } amber_batch_item;
 
-/* Workspace for amber_batch_run over these items: the largest single-box
- * requirement (boxes run one after another and share it). 0 on bad input. */
-size_t amber_batch_workspace_bytes(const amber_batch_item* items, int n_items);
+/* Side streams and events on which amber_batch_run runs boxes concurrently
+ * ("lanes"): lane 0 is the caller's stream, lanes 1..n_lanes-1 are streams the
+ * executor creates (default priority, non-blocking) with one event each, plus
+ * one fork event.  Created once, outside any timed or captured region, on the
+ * device that is current; destroyed by amber_executor_destroy.  n_lanes in
+ * 1..16.  An executor must not be used by two host threads at once. */
+typedef struct amber_executor_s* amber_executor;
+int amber_executor_create(amber_executor* out, int n_lanes);
+void amber_executor_destroy(amber_executor ex);
 
-/* Enqueues every box of the batch on `stream`, in order.  All items are
- * checked on the host before anything is enqueued (the first error is
- * returned and nothing runs).  d_status (optional, device, n_items unsigned)
- * receives the OR of each box's device status bits (AMBER_STATUS_*).  Only
- * kernels are enqueued (no allocation, copy, memset or synchronisation), so a
- * batch can be captured into a HIP graph and replayed; per-kernel timing
- * (amber_profile_begin) must be off while capturing. */
+/* Workspace for amber_batch_run over these items on n_lanes lanes: n_lanes
+ * slices of the largest single-box requirement (each lane runs its boxes one
+ * after another in its own slice). 0 on bad input. */
+size_t amber_batch_workspace_bytes(const amber_batch_item* items, int n_items, int n_lanes);
+
+/* Runs every box of the batch (Sec. 3.4: each box's radiation fields, then
+ * the matching of each field against its histories).  With ex NULL the boxes
+ * run in order on `stream`.  With an executor of L lanes the boxes are dealt
+ * to the lanes, largest first (cost N^3 times the number of fields), each lane
+ * taking the box with the least accumulated cost; the lanes fork from `stream`
+ * (an event recorded on it) and join back into it (one event per side lane),
+ * so the work after the call on `stream` sees every result, and the whole
+ * call can be captured into a HIP graph from `stream`.  Results do not depend
+ * on the lanes: each box computes exactly what its single calls compute.
+ * Entries of d_zre may be NULL: that (l, h) pair is not matched, and a field
+ * with no requested history is not ranked (a sparse set of pairs per box).
+ * All items are checked on the host before anything is enqueued (the first
+ * error is returned and nothing runs).  d_status (optional, device, n_items
+ * unsigned) receives the OR of each box's device status bits (AMBER_STATUS_*).
+ * Only kernels and event records/waits are enqueued (no allocation, copy,
+ * memset or synchronisation); per-kernel timing (amber_profile_begin) must be
+ * off while capturing. */
 int amber_batch_run(const amber_batch_item* items, int n_items, unsigned* d_status, void* d_ws, size_t ws_bytes,
-                    void* stream);
+                    void* stream, amber_executor ex);
 
 /* ---- per-kernel timing (tracing aid, not needed for results) ------------ */
 

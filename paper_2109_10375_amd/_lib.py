@@ -27,6 +27,7 @@ SYMBOLS = [
     "amber_spectra", "amber_growth_table", "amber_halo_workspace_bytes", "amber_radiation_from_halos",
     "amber_fft_schedules", "amber_fft_schedule_info", "amber_plan_set_schedule", "amber_plan_get_schedule",
     "amber_plan_tune", "amber_history_prepare", "amber_growth_prepare", "amber_zre_noalloc",
+    "amber_executor_create", "amber_executor_destroy",
 ]
 NOALLOC_MAX_N = 128
 NOALLOC_SCRATCH_BYTES = 68 << 20
@@ -104,9 +105,12 @@ def lib() -> ctypes.CDLL:
         L.amber_growth_prepare.argtypes = [ctypes.POINTER(AmberWeibull), d, d, vp, sz, vp]
         L.amber_profile_begin.argtypes = [vp, i]
         L.amber_profile_end.argtypes = [vp, ctypes.POINTER(AmberKernelTime), i, ctypes.POINTER(i)]
-        L.amber_batch_workspace_bytes.argtypes = [ctypes.POINTER(AmberBatchItem), i]
+        L.amber_batch_workspace_bytes.argtypes = [ctypes.POINTER(AmberBatchItem), i, i]
         L.amber_batch_workspace_bytes.restype = sz
-        L.amber_batch_run.argtypes = [ctypes.POINTER(AmberBatchItem), i, vp, vp, sz, vp]
+        L.amber_batch_run.argtypes = [ctypes.POINTER(AmberBatchItem), i, vp, vp, sz, vp, vp]
+        L.amber_executor_create.argtypes = [ctypes.POINTER(vp), i]
+        L.amber_executor_destroy.argtypes = [vp]
+        L.amber_executor_destroy.restype = None
         L.amber_spectra_workspace_bytes.argtypes = [vp]
         L.amber_spectra_workspace_bytes.restype = sz
         L.amber_spectra.argtypes = [vp, vp, i, vp, i, i, vp, vp, sz, vp]
@@ -402,10 +406,12 @@ class Plan:
 
 class BatchItem:
     """One box of a batch (amber_batch_item): its fields, mean free paths and
-    histories.  z_re of J_l under history h is zre[l][h]."""
+    histories.  z_re of J_l under history h is zre[l][h]; an entry may be None
+    (that pair is not matched)."""
 
     def __init__(self, plan: Plan, S: torch.Tensor | None, w: torch.Tensor, l_mfp: Sequence[float],
-                 J: Sequence[torch.Tensor], hists: Sequence[History], zre: Sequence[Sequence[torch.Tensor]]):
+                 J: Sequence[torch.Tensor], hists: Sequence[History],
+                 zre: Sequence[Sequence[torch.Tensor | None]]):
         nl, nh = len(J), len(hists)
         if S is not None and len(l_mfp) != nl:
             raise ValueError("one J field per mean free path")
@@ -417,7 +423,8 @@ class BatchItem:
         self._J = (ctypes.c_void_p * nl)(*[_dev_ptr(t, torch.float32, n3, "J").value for t in J])
         self._h = (AmberWeibull * nh)(*[h.w for h in hists])
         flat = [z for row in zre for z in row]
-        self._z = (ctypes.c_void_p * len(flat))(*[_dev_ptr(t, torch.float32, n3, "z_re").value for t in flat])
+        self._z = (ctypes.c_void_p * len(flat))(*[None if t is None else _dev_ptr(t, torch.float32, n3, "z_re").value
+                                                  for t in flat])
         self.c = AmberBatchItem(plan._h.value, _dev_ptr(S, torch.float32, n3, "S").value if S is not None else None,
                                 _dev_ptr(w, torch.float32, n3, "w").value, nl,
                                 ctypes.cast(self._l, ctypes.POINTER(ctypes.c_double)),
@@ -426,13 +433,32 @@ class BatchItem:
                                 ctypes.cast(self._z, ctypes.POINTER(ctypes.c_void_p)))
 
 
-class Batch:
-    """A fixed list of boxes run by amber_batch_run with one shared workspace."""
+class Executor:
+    """Side streams and events for running the boxes of a batch concurrently
+    (amber_executor_create); lane 0 is the calling stream."""
 
-    def __init__(self, items: Sequence[BatchItem], ws: torch.Tensor | None = None):
+    def __init__(self, lanes: int):
+        h = ctypes.c_void_p()
+        _check(lib().amber_executor_create(ctypes.byref(h), int(lanes)), "amber_executor_create")
+        self._h = h
+        self.lanes = int(lanes)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.amber_executor_destroy(h)
+            self._h = None
+
+
+class Batch:
+    """A fixed list of boxes run by amber_batch_run with one workspace (one
+    slice per lane)."""
+
+    def __init__(self, items: Sequence[BatchItem], ws: torch.Tensor | None = None, lanes: int = 1):
         self.items = list(items)
+        self.lanes = max(1, min(int(lanes), len(self.items)))
         self._arr = (AmberBatchItem * len(self.items))(*[it.c for it in self.items])
-        need = int(lib().amber_batch_workspace_bytes(self._arr, len(self.items)))
+        need = int(lib().amber_batch_workspace_bytes(self._arr, len(self.items), self.lanes))
         if need == 0:
             raise ValueError("invalid batch")
         self.device = self.items[0].plan.device
@@ -440,14 +466,16 @@ class Batch:
             raise ValueError(f"workspace: expected a CUDA uint8 tensor of at least {need} bytes")
         self.ws = ws if ws is not None else torch.empty(need, dtype=torch.uint8, device=self.device)
         self.status = torch.zeros(len(self.items), dtype=torch.int32, device=self.device)
+        self.executor = Executor(self.lanes) if self.lanes > 1 else None
 
     @staticmethod
-    def workspace_bytes(items: Sequence[BatchItem]) -> int:
+    def workspace_bytes(items: Sequence[BatchItem], lanes: int = 1) -> int:
         arr = (AmberBatchItem * len(items))(*[it.c for it in items])
-        return int(lib().amber_batch_workspace_bytes(arr, len(items)))
+        return int(lib().amber_batch_workspace_bytes(arr, len(items), max(1, min(int(lanes), len(items)))))
 
     def run(self) -> None:
         """amber_batch_run on torch's current stream; per-box status bits land in self.status."""
+        ex = self.executor._h if self.executor is not None else None
         _check(lib().amber_batch_run(self._arr, len(self.items), ctypes.c_void_p(self.status.data_ptr()),
-                                     ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream()),
+                                     ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream(), ex),
                "amber_batch_run")

@@ -597,8 +597,6 @@ static int check_item(const amber_batch_item& it) {
             if ((const void*)it.d_J[i] == (const void*)it.d_src) return AMBER_E_ARG;
         }
     }
-    for (int i = 0; i < it.n_lmfp * it.n_hist; ++i)
-        if (!it.d_zre[i]) return AMBER_E_ARG;
     for (int h = 0; h < it.n_hist; ++h) {
         const int rc = check_weibull(it.hist[h]);
         if (rc != AMBER_OK) return rc;
@@ -606,48 +604,149 @@ static int check_item(const amber_batch_item& it) {
     return AMBER_OK;
 }
 
-size_t amber_batch_workspace_bytes(const amber_batch_item* items, int n_items) {
-    if (!items || n_items < 1) return 0;
+// Workspace of one box of a batch (radiation with all its fields, or matching only).
+static size_t item_ws_bytes(const amber_batch_item& it) {
+    const int nl = it.d_src ? std::max(1, it.n_lmfp) : 1;
+    return ws_layout(it.plan->n, nl).total;
+}
+
+// One box: its radiation fields, then each field's wanted histories
+// (consecutive non-NULL outputs share one ranking), on one stream and one
+// workspace slice.
+static int run_item(const amber_batch_item& it, unsigned* d_status, unsigned char* ws, hipStream_t s) {
+    const amber_plan_s* p = it.plan;
+    if (it.d_src) {
+        const WsLayout LR = ws_layout(p->n, it.n_lmfp);
+        const int rc = fft_radiation(p, it.d_src, it.l_mfp, it.n_lmfp, it.d_J, ws, LR, s);
+        if (rc != AMBER_OK) return rc;
+    }
+    const WsLayout L = ws_layout(p->n, 1);
+    if (d_status) {
+        const int rc = status_collect(p, ws, L, d_status, true, s);
+        if (rc != AMBER_OK) return rc;
+    }
+    for (int l = 0; l < it.n_lmfp; ++l) {
+        amber_weibull hs[8];
+        float* zs[8];
+        int k = 0;
+        for (int h = 0; h < it.n_hist; ++h) {
+            float* z = it.d_zre[(size_t)l * it.n_hist + h];
+            if (!z) continue;
+            hs[k] = it.hist[h];
+            zs[k] = z;
+            ++k;
+        }
+        if (k == 0) continue;
+        int rc = rank_sort(p, it.d_J[l], it.d_w, ws, L, s, 1, nullptr);
+        if (rc == AMBER_OK) rc = match_scan(p, hs, k, zs, ws, L, s);
+        if (rc == AMBER_OK && d_status) rc = status_collect(p, ws, L, d_status, false, s);
+        if (rc != AMBER_OK) return rc;
+    }
+    return AMBER_OK;
+}
+
+int amber_executor_create(amber_executor* out, int n_lanes) {
+    if (!out || n_lanes < 1 || n_lanes > 16) return AMBER_E_ARG;
+    *out = nullptr;
+    amber_executor_s* ex = new (std::nothrow) amber_executor_s();
+    if (!ex) return AMBER_E_ARG;
+    ex->n_lanes = n_lanes;
+    hipError_t e = hipGetDevice(&ex->device);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ex->fork, hipEventDisableTiming);
+    for (int l = 1; e == hipSuccess && l < n_lanes; ++l) {
+        e = hipStreamCreateWithFlags(&ex->side[l], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ex->join[l], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        amber_executor_destroy(ex);
+        return AMBER_E_HIP;
+    }
+    *out = ex;
+    return AMBER_OK;
+}
+
+void amber_executor_destroy(amber_executor ex) {
+    if (!ex) return;
+    for (int l = 1; l < 16; ++l) {
+        if (ex->side[l]) {
+            (void)hipStreamSynchronize(ex->side[l]);
+            (void)hipStreamDestroy(ex->side[l]);
+        }
+        if (ex->join[l]) (void)hipEventDestroy(ex->join[l]);
+    }
+    if (ex->fork) (void)hipEventDestroy(ex->fork);
+    delete ex;
+}
+
+size_t amber_batch_workspace_bytes(const amber_batch_item* items, int n_items, int n_lanes) {
+    if (!items || n_items < 1 || n_lanes < 1 || n_lanes > 16) return 0;
     size_t need = 0;
     for (int i = 0; i < n_items; ++i) {
         if (!items[i].plan) return 0;
-        const int nl = items[i].d_src ? std::max(1, items[i].n_lmfp) : 1;
-        need = std::max(need, ws_layout(items[i].plan->n, nl).total);
+        need = std::max(need, item_ws_bytes(items[i]));
     }
-    return need;
+    return align256(need) * (size_t)std::min(n_lanes, n_items);
 }
 
 int amber_batch_run(const amber_batch_item* items, int n_items, unsigned* d_status, void* d_ws, size_t ws_bytes,
-                    void* stream) {
-    if (!items || n_items < 1 || !d_ws) return AMBER_E_ARG;
+                    void* stream, amber_executor ex) {
+    if (!items || n_items < 1 || n_items > (1 << 20) || !d_ws) return AMBER_E_ARG;
     for (int i = 0; i < n_items; ++i) {
         const int rc = check_item(items[i]);
         if (rc != AMBER_OK) return rc;
     }
-    if (ws_bytes < amber_batch_workspace_bytes(items, n_items)) return AMBER_E_WORKSPACE;
+    const int lanes = ex ? std::min(ex->n_lanes, n_items) : 1;
+    if (ws_bytes < amber_batch_workspace_bytes(items, n_items, lanes)) return AMBER_E_WORKSPACE;
     unsigned char* ws = static_cast<unsigned char*>(d_ws);
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int i = 0; i < n_items; ++i) {
-        const amber_batch_item& it = items[i];
-        const amber_plan_s* p = it.plan;
-        if (it.d_src) {
-            const WsLayout LR = ws_layout(p->n, it.n_lmfp);
-            const int rc = fft_radiation(p, it.d_src, it.l_mfp, it.n_lmfp, it.d_J, ws, LR, s);
+    if (lanes == 1) {
+        for (int i = 0; i < n_items; ++i) {
+            const int rc = run_item(items[i], d_status ? d_status + i : nullptr, ws, s);
             if (rc != AMBER_OK) return rc;
         }
-        const WsLayout L = ws_layout(p->n, 1);
-        if (d_status) {
-            const int rc = status_collect(p, ws, L, d_status + i, true, s);
-            if (rc != AMBER_OK) return rc;
-        }
-        for (int l = 0; l < it.n_lmfp; ++l) {
-            int rc = rank_sort(p, it.d_J[l], it.d_w, ws, L, s, 1, nullptr);
-            if (rc == AMBER_OK) rc = match_scan(p, it.hist, it.n_hist, it.d_zre + (size_t)l * it.n_hist, ws, L, s);
-            if (rc == AMBER_OK && d_status) rc = status_collect(p, ws, L, d_status + i, false, s);
-            if (rc != AMBER_OK) return rc;
-        }
+        return AMBER_OK;
     }
-    return AMBER_OK;
+    // Deal the boxes to the lanes: largest first, each to the least loaded lane.
+    const size_t slice = align256(amber_batch_workspace_bytes(items, n_items, 1));
+    int* order = new (std::nothrow) int[(size_t)n_items];
+    int* lane_of = new (std::nothrow) int[(size_t)n_items];
+    if (!order || !lane_of) {
+        delete[] order;
+        delete[] lane_of;
+        return AMBER_E_ARG;
+    }
+    auto cost = [&](int i) {
+        const double n3 = (double)items[i].plan->n * items[i].plan->n * items[i].plan->n;
+        return n3 * (double)items[i].n_lmfp;
+    };
+    for (int i = 0; i < n_items; ++i) order[i] = i;
+    std::stable_sort(order, order + n_items, [&](int a, int b) { return cost(a) > cost(b); });
+    double load[16] = {};
+    for (int k = 0; k < n_items; ++k) {
+        int best = 0;
+        for (int l = 1; l < lanes; ++l)
+            if (load[l] < load[best]) best = l;
+        lane_of[order[k]] = best;
+        load[best] += cost(order[k]);
+    }
+    int rc = AMBER_OK;
+    if (hipEventRecord(ex->fork, s) != hipSuccess) rc = AMBER_E_HIP;
+    for (int l = 1; rc == AMBER_OK && l < lanes; ++l)
+        if (hipStreamWaitEvent(ex->side[l], ex->fork, 0) != hipSuccess) rc = AMBER_E_HIP;
+    // each lane's boxes in the order they were dealt
+    for (int k = 0; rc == AMBER_OK && k < n_items; ++k) {
+        const int i = order[k], l = lane_of[i];
+        rc = run_item(items[i], d_status ? d_status + i : nullptr, ws + (size_t)l * slice, l == 0 ? s : ex->side[l]);
+    }
+    // join every side lane back into the caller's stream (also after an error,
+    // so that no captured fork is left open)
+    for (int l = 1; l < lanes; ++l) {
+        if (hipEventRecord(ex->join[l], ex->side[l]) != hipSuccess || hipStreamWaitEvent(s, ex->join[l], 0) != hipSuccess)
+            if (rc == AMBER_OK) rc = AMBER_E_HIP;
+    }
+    delete[] order;
+    delete[] lane_of;
+    return rc;
 }
 
 size_t amber_spectra_workspace_bytes(amber_plan plan) {

@@ -30,6 +30,15 @@ struct amber_plan_s {
     Profiler* prof = nullptr;
 };
 
+// Lanes of a concurrent batch: the side streams and their events.
+struct amber_executor_s {
+    int n_lanes = 1;
+    int device = -1;
+    hipStream_t side[16] = {};     // lanes 1..n_lanes-1
+    hipEvent_t fork = nullptr;     // recorded on the caller's stream
+    hipEvent_t join[16] = {};      // recorded on each side lane
+};
+
 inline int prof_start(const amber_plan_s* p, const char* name, hipStream_t s) {
     Profiler* f = p->prof;
     if (!f) return -1;

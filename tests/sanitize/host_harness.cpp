@@ -98,7 +98,10 @@ int main() {
     EXPECT(amber_radiation(nullptr, dummy, nullptr, 1, outs, dummy, 0, nullptr) == AMBER_E_ARG);
     EXPECT(amber_zre(nullptr, dummy, dummy, &w, 1, outs, dummy, 0, nullptr) == AMBER_E_ARG);
     EXPECT(amber_workspace_bytes(nullptr, 1, 1) == 0);
-    EXPECT(amber_batch_workspace_bytes(nullptr, 0) == 0);
+    EXPECT(amber_batch_workspace_bytes(nullptr, 0, 1) == 0);
+    EXPECT(amber_batch_run(nullptr, 1, nullptr, nullptr, 0, nullptr, nullptr) == AMBER_E_ARG);
+    amber_executor ex = nullptr;
+    EXPECT(amber_executor_create(&ex, 0) == AMBER_E_ARG && ex == nullptr);
     unsigned st = 0;
     EXPECT(amber_status(nullptr, nullptr, &st) == AMBER_E_ARG);
     amber_plan plan = nullptr;

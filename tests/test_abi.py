@@ -107,13 +107,17 @@ def test_batch_entry_points_check_their_arguments_on_the_host():
     L = amber.lib()
     assert "amber_batch_run" in _declared_symbols() and "amber_batch_workspace_bytes" in _declared_symbols()
     Item = amber._lib.AmberBatchItem
-    assert L.amber_batch_workspace_bytes(None, 0) == 0
+    assert L.amber_batch_workspace_bytes(None, 0, 1) == 0
     items = (Item * 1)()
-    assert L.amber_batch_workspace_bytes(items, 1) == 0  # no plan
-    assert L.amber_batch_run(None, 1, None, None, 0, None) == amber._lib.E_ARG
-    assert L.amber_batch_run(items, 0, None, ctypes.c_void_p(1), 1, None) == amber._lib.E_ARG
+    assert L.amber_batch_workspace_bytes(items, 1, 1) == 0  # no plan
+    assert L.amber_batch_workspace_bytes(items, 1, 17) == 0  # too many lanes
+    assert L.amber_batch_run(None, 1, None, None, 0, None, None) == amber._lib.E_ARG
+    assert L.amber_batch_run(items, 0, None, ctypes.c_void_p(1), 1, None, None) == amber._lib.E_ARG
     # an item with no plan is rejected before anything is enqueued
-    assert L.amber_batch_run(items, 1, None, ctypes.c_void_p(1), 1, None) == amber._lib.E_ARG
+    assert L.amber_batch_run(items, 1, None, ctypes.c_void_p(1), 1, None, None) == amber._lib.E_ARG
+    ex = ctypes.c_void_p()
+    assert L.amber_executor_create(ctypes.byref(ex), 0) == amber._lib.E_ARG
+    assert L.amber_executor_create(ctypes.byref(ex), 17) == amber._lib.E_ARG
 
 
 @pytest.mark.parametrize("hist,z_mid,om", [((8.0, 4.0, 3.0), 8.0, 0.3), ((7.83, 6.54, 2.33), 7.83, 0.3),

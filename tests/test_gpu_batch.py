@@ -178,10 +178,45 @@ def test_sweep_512_full(amber):
     assert torch.equal(z1, Z[3][2])
 
 
+def test_sparse_pairs_and_lanes(amber):
+    """A box with a sparse set of (l_mfp, history) outputs (None entries are
+    not matched; a field with none is not ranked) next to other boxes, run on
+    three lanes: every requested field equals the single calls."""
+    dev = torch.device("cuda", 0)
+    items, keep = [], []
+    for b, n in enumerate((64, 96, 32, 64)):
+        cfg = inputs.BoxConfig(f"sp{b}", n, 1.953125 * n, max(1000, n ** 3 // 20), 1e10, 1e12, index=70 + b)
+        w, S = inputs.make_box(cfg, device=dev, dtype=torch.float32)
+        ls = [1.0, 3.0, 10.0]
+        ors, gh = _hists(amber, [(8.0, 4.0, 3.0), (7.83, 6.54, 2.33)])
+        plan = amber.Plan(n, cfg.box_len)
+        J = _empty(n, len(ls), dev)
+        want = [[(l + h + b) % 2 == 0 for h in range(2)] for l in range(3)]
+        want[2] = [False, False]          # this field is computed but not matched
+        Z = [[torch.full((n, n, n), -7.0, device=dev) if want[l][h] else None for h in range(2)] for l in range(3)]
+        items.append(amber.BatchItem(plan, S, w, ls, J, gh, Z))
+        keep.append((plan, S, w, ls, gh, J, Z))
+    batch = amber.Batch(items, lanes=3)
+    batch.run()
+    torch.cuda.synchronize()
+    assert batch.status.cpu().tolist() == [0] * len(items)
+    for plan, S, w, ls, gh, J, Z in keep:
+        Js = plan.radiation(S, ls)
+        for l in range(3):
+            assert torch.equal(J[l], Js[l])
+            for h in range(2):
+                if Z[l][h] is not None:
+                    (z1,) = plan.zre(Js[l], w, [gh[h]])
+                    torch.cuda.synchronize()
+                    assert torch.equal(Z[l][h], z1), (plan.n, l, h)
+
+
 def test_mixed_batch_graph_replay(amber):
     """Eight boxes of the mixed-size recipe, eager and as a captured HIP graph
     replayed three times with other device work in between: every replay
-    equals the eager result bit for bit."""
+    equals the eager result bit for bit.  The same boxes on four lanes
+    (concurrent streams forked from and joined into the capturing stream),
+    eager and captured, give the same fields."""
     dev = torch.device("cuda", 0)
     cfgs = inputs.c4_boxes(8)
     items, keep = [], []
@@ -230,3 +265,34 @@ def test_mixed_batch_graph_replay(amber):
             assert torch.equal(Z[0][0], ref_Z[b]), (rep, b)
         assert batch.status.cpu().tolist() == [0] * len(items)
         print(f"graph replay {rep}: equal to eager", flush=True)
+
+    lanes = amber.Batch(items, lanes=4)
+    for (_, _, _, _, J, Z) in keep:
+        J[0].zero_()
+        Z[0][0].zero_()
+    lanes.run()
+    torch.cuda.synchronize()
+    assert lanes.status.cpu().tolist() == [0] * len(items)
+    for b, (_, _, _, _, J, Z) in enumerate(keep):
+        assert torch.equal(J[0], ref_J[b]) and torch.equal(Z[0][0], ref_Z[b]), b
+    g4 = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g4, stream=side):
+            lanes.run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for (_, _, _, _, J, Z) in keep:
+            J[0].zero_()
+            Z[0][0].zero_()
+        other.radiation(S_other, [5.0 + rep])
+        torch.cuda.synchronize()
+        g4.replay()
+        torch.cuda.synchronize()
+        for b, (_, _, _, _, J, Z) in enumerate(keep):
+            assert torch.equal(J[0], ref_J[b]), (rep, b)
+            assert torch.equal(Z[0][0], ref_Z[b]), (rep, b)
+        assert lanes.status.cpu().tolist() == [0] * len(items)
+        print(f"four-lane graph replay {rep}: equal to eager", flush=True)

@@ -1,8 +1,11 @@
 """Continuous-batching serving (paper_2109_10375_amd.serve): requests of
 several grid sizes arrive together, are batched per grid size and run on
-several streams at once; every served J and z_re must equal, bit for bit, the
-same request run alone through amber_radiation and amber_zre (reading B1: a
-batch is the same work as its single calls)."""
+several streams at once, requests of one box merged into one batch item
+(shared forward transform, one ranking per mean free path, a sparse set of
+(l_mfp, history) outputs); every served J and z_re must equal, bit for bit,
+the same request run alone through amber_radiation and amber_zre (reading B1:
+a batch is the same work as its single calls).  The plain single-box path
+(one request at a time) serves the same requests with the same results."""
 import numpy as np
 import pytest
 import torch
@@ -28,15 +31,21 @@ def test_served_results_equal_each_request_alone():
     hists = ((8.0, 4.0, 3.0), (7.95, 4.68, 2.90), (7.83, 6.54, 2.33))
     reqs = [serve.Request(float(0.002 * k), int(rng.choice([32, 64, 96])), float(rng.choice(lmfp)),
                           hists[int(rng.integers(0, 3))]) for k in range(18)]
-    server = serve.Server(boxes, hbm_budget_bytes=1 << 30, max_batch=3, slots=3)
+    server = serve.Server(boxes, hbm_budget_bytes=1 << 30, max_batch=4, slots=3)
     st = server.serve(reqs, keep_outputs=True)
     torch.cuda.synchronize()
-    print(f"served {st['requests']} requests in {st['batches']} batches, "
+    print(f"served {st['requests']} requests in {st['batches']} batches ({st['requests_merged']} merged), "
           f"at most {st['max_batches_in_flight']} in flight", flush=True)
     assert st["requests"] == len(reqs)
     assert st["max_batches_in_flight"] >= 2
+    assert st["requests_merged"] >= 1
+    fifo = serve.Server(boxes, hbm_budget_bytes=1 << 30, max_batch=1, slots=1, merge=False)
+    sf = fifo.serve(reqs, keep_outputs=True)
+    torch.cuda.synchronize()
+    assert sf["batches"] == len(reqs) and sf["max_batches_in_flight"] == 1
     order = sorted(reqs, key=lambda r: r.t_arrival)
-    for r, (J, z) in zip(order, st["outputs"]):
+    for r, (J, z), (Jf, zf) in zip(order, st["outputs"], sf["outputs"]):
+        assert torch.equal(J, Jf) and torch.equal(z, zf)
         box = boxes[r.n]
         (Ja,) = box.plan.radiation(box.S, [r.l_mfp])
         (za,) = box.plan.zre(Ja, box.w, [amber.History.from_params(*r.history)])
