@@ -29,9 +29,10 @@ def test_served_results_equal_each_request_alone():
     rng = np.random.default_rng(31)
     lmfp = (0.5, 3.0, 20.0)
     hists = ((8.0, 4.0, 3.0), (7.95, 4.68, 2.90), (7.83, 6.54, 2.33))
-    reqs = [serve.Request(float(0.002 * k), int(rng.choice([32, 64, 96])), float(rng.choice(lmfp)),
+    # the requests arrive within a few hundred microseconds: they queue, merge and overlap
+    reqs = [serve.Request(float(2e-5 * k), int(rng.choice([32, 64, 96])), float(rng.choice(lmfp)),
                           hists[int(rng.integers(0, 3))]) for k in range(18)]
-    server = serve.Server(boxes, hbm_budget_bytes=1 << 30, max_batch=4, slots=3)
+    server = serve.Server(boxes, hbm_budget_bytes=1 << 30, max_batch=4, slots=3, exclusive_from=1 << 20)
     st = server.serve(reqs, keep_outputs=True)
     torch.cuda.synchronize()
     print(f"served {st['requests']} requests in {st['batches']} batches ({st['requests_merged']} merged), "
@@ -39,13 +40,17 @@ def test_served_results_equal_each_request_alone():
     assert st["requests"] == len(reqs)
     assert st["max_batches_in_flight"] >= 2
     assert st["requests_merged"] >= 1
+    # the largest grid run alone (the default), and the one-at-a-time path
+    excl = serve.Server(boxes, hbm_budget_bytes=1 << 30, max_batch=4, slots=3)
+    se = excl.serve(reqs, keep_outputs=True)
     fifo = serve.Server(boxes, hbm_budget_bytes=1 << 30, max_batch=1, slots=1, merge=False)
     sf = fifo.serve(reqs, keep_outputs=True)
     torch.cuda.synchronize()
     assert sf["batches"] == len(reqs) and sf["max_batches_in_flight"] == 1
     order = sorted(reqs, key=lambda r: r.t_arrival)
-    for r, (J, z), (Jf, zf) in zip(order, st["outputs"], sf["outputs"]):
+    for r, (J, z), (Je, ze), (Jf, zf) in zip(order, st["outputs"], se["outputs"], sf["outputs"]):
         assert torch.equal(J, Jf) and torch.equal(z, zf)
+        assert torch.equal(J, Je) and torch.equal(z, ze)
         box = boxes[r.n]
         (Ja,) = box.plan.radiation(box.S, [r.l_mfp])
         (za,) = box.plan.zre(Ja, box.w, [amber.History.from_params(*r.history)])
