@@ -189,28 +189,107 @@ __device__ __forceinline__ int growth_gap_sign(double ks, double ns, double cn, 
     return g > 0.0 ? 1 : (g <= 0.0 ? 0 : -1);
 }
 
-__device__ double invert_growth(double ks, double ns, double cn, double cN, double a, double h, long long T,
-                                double z_top, const double2* __restrict__ XG) {
-#pragma clang fp contract(off)
-    const double2 n0 = XG[0], nT = XG[T];
-    if (growth_gap_sign(ks, ns, cn, cN, n0.y, n0.x) == 1) return a;
-    if (growth_gap_sign(ks, ns, cn, cN, nT.y, nT.x) != 1) return z_top;
-    long long lo = 0, hi = T;
-    while (hi - lo > 1) {
-        const long long mid = lo + (hi - lo) / 2;
-        const double2 nm = XG[mid];  // X and G of the node in one read
-        if (growth_gap_sign(ks, ns, cn, cN, nm.y, nm.x) == 0) {
-            lo = mid;
-        } else {
-            hi = mid;
+// The bracket of one rank: -1 when h_0 > 0 (z = a), T when h_T <= 0 (z =
+// z_top), otherwise lo with h_lo <= 0 < h_{lo+1}.  Where the gap changes sign
+// once over the nodes this answer is unique, so any search that finds a sign
+// change finds it.  The search starts from hint (a bracket of the same kind
+// found for a nearby rank), checks it, and otherwise gallops away from it in
+// the direction of the sign change and bisects the last step.
+__device__ long long growth_bracket(double ks, double ns, double cn, double cN, long long T,
+                                    const double2* __restrict__ XG, long long hint) {
+    auto sgn = [&](long long j) {
+        const double2 nd = XG[j];  // X and G of the node in one read
+        return growth_gap_sign(ks, ns, cn, cN, nd.y, nd.x);
+    };
+    long long lo, hi;  // sgn(lo) == 0 (h <= 0), sgn(hi) != 0 (h > 0 or unordered)
+    if (hint < 0) {
+        if (sgn(0) != 0) return -1;
+        hint = 0;
+    } else if (hint >= T) {
+        if (sgn(T) == 0) return T;
+        hint = T - 1;
+    }
+    if (sgn(hint) == 0) {
+        if (sgn(hint + 1) != 0) return hint;  // the hint's bracket
+        // the crossing lies above: gallop up
+        long long step = 2, a = hint + 1;
+        for (;;) {
+            const long long b = a + step < T ? a + step : T;
+            if (sgn(b) != 0) {
+                lo = a;
+                hi = b;
+                break;
+            }
+            if (b == T) return T;
+            a = b;
+            step *= 2;
+        }
+    } else {
+        // the crossing lies below: gallop down
+        long long step = 1, b = hint;
+        for (;;) {
+            const long long a = b - step > 0 ? b - step : 0;
+            if (sgn(a) == 0) {
+                lo = a;
+                hi = b;
+                break;
+            }
+            if (a == 0) return -1;
+            b = a;
+            step *= 2;
         }
     }
-    // the gaps at the bracket, as the interpolation needs their values
-    const double2 nl = XG[lo], nh = XG[hi];
+    while (hi - lo > 1) {
+        const long long mid = lo + (hi - lo) / 2;
+        if (sgn(mid) == 0) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// The same kind of bracket for one rank, searched by the 64 lanes of a wave
+// together (every lane calls it with the same arguments): each round the lanes
+// test 64 evenly spaced nodes of the current interval and keep the one
+// between the last non-positive and the first positive gap, so 2^22 nodes take
+// four rounds of reads in flight together.
+__device__ long long wave_growth_bracket(double ks, double ns, double cn, double cN, long long T,
+                                         const double2* __restrict__ XG) {
+    const int lane = threadIdx.x & 63;
+    auto sgn = [&](long long j) {
+        const double2 nd = XG[j];
+        return growth_gap_sign(ks, ns, cn, cN, nd.y, nd.x);
+    };
+    const int sp = sgn(lane == 0 ? 0 : T);
+    const int s0 = __shfl(sp, 0, 64), sT = __shfl(sp, 1, 64);
+    if (s0 == 1) return -1;
+    if (sT != 1) return T;
+    long long lo = 0, hi = T;
+    while (hi - lo > 1) {
+        const long long step = (hi - lo + 63) / 64;
+        const long long node = lo + (long long)(lane + 1) * step;  // lane 63's node is at or past hi
+        const bool pos = node >= hi ? true : (sgn(node) != 0);
+        const unsigned long long m = __ballot(pos);
+        const int first = __ffsll((long long)m) - 1;
+        const long long nh = lo + (long long)(first + 1) * step;
+        lo = lo + (long long)first * step;
+        hi = nh < hi ? nh : hi;
+    }
+    return lo;
+}
+
+// z from a bracket whose two nodes' (X, G) pairs are at hand (nl for lo, nh
+// for lo + 1): z = z_lo + t (z_hi - z_lo), t = -h_lo / (h_hi - h_lo), min
+// z_top (FP64, this operation order, no fused multiply-add); a for lo < 0,
+// z_top for lo >= T.
+__device__ __forceinline__ double growth_z(long long lo, double ks, double ns, double cn, double cN, double a,
+                                           double h, long long T, double z_top, double2 nl, double2 nh) {
+#pragma clang fp contract(off)
+    if (lo < 0) return a;
+    if (lo >= T) return z_top;
     const double hlo = growth_gap(ks, ns, cn, cN, nl.y, nl.x);
     const double hhi = growth_gap(ks, ns, cn, cN, nh.y, nh.x);
     const double zl = a + (double)lo * h;
-    const double zh = a + (double)hi * h;
+    const double zh = a + (double)(lo + 1) * h;
     const double t = -hlo / (hhi - hlo);
     const double z = zl + t * (zh - zl);
     return (z < z_top) ? z : z_top;
@@ -561,12 +640,37 @@ void k_scan_partition(
 #pragma clang fp contract(off)
         if constexpr (GROWTH) {
             if (H.XG) {
+                // consecutive ranks nearly always share a bracket: the wave
+                // brackets its first rank together, each rank first checks the
+                // previous rank's bracket with the two nodes kept in registers
+                // and searches (from that bracket) only when it has moved
+                long long lo = wave_growth_bracket(__shfl((double)(p0 + 1) * unit, 0, 64), ns,
+                                                   __shfl(cn[0], 0, 64), tot, H.T, H.XG);
+                double2 nl, nh;  // (X, G) of nodes lo and lo + 1, clamped to [0, T]
+                auto load_pair = [&](long long l) {
+                    nl = H.XG[l < 0 ? 0 : (l > H.T ? H.T : l)];
+                    nh = H.XG[l + 1 > H.T ? H.T : (l + 1 < 0 ? 0 : l + 1)];
+                };
+                load_pair(lo);
 #pragma unroll
                 for (int j = 0; j < kPer; ++j) {
+                    zf[j] = 0.0f;
+                    if (pos[j] == 0xffffffffu) continue;
                     const double ks = (double)(p0 + j + 1) * unit;
-                    zf[j] = pos[j] != 0xffffffffu
-                                ? (float)invert_growth(ks, ns, cn[j], tot, H.a, H.h, H.T, H.z_top, H.XG)
-                                : 0.0f;
+                    bool same;
+                    if (lo < 0) {
+                        same = growth_gap_sign(ks, ns, cn[j], tot, nl.y, nl.x) != 0;   // node 0: h_0 > 0
+                    } else if (lo >= H.T) {
+                        same = growth_gap_sign(ks, ns, cn[j], tot, nl.y, nl.x) == 0;   // node T: h_T <= 0
+                    } else {
+                        same = growth_gap_sign(ks, ns, cn[j], tot, nl.y, nl.x) == 0 &&
+                               growth_gap_sign(ks, ns, cn[j], tot, nh.y, nh.x) != 0;
+                    }
+                    if (!same) {
+                        lo = growth_bracket(ks, ns, cn[j], tot, H.T, H.XG, lo);
+                        load_pair(lo);
+                    }
+                    zf[j] = (float)growth_z(lo, ks, ns, cn[j], tot, H.a, H.h, H.T, H.z_top, nl, nh);
                 }
                 return;
             }
