@@ -188,31 +188,89 @@ struct Dft<4, INV> {
 // L1 | L2.  On entry v[j] = x[t + L1 j]; on exit v[j] = X[t + L1 j].
 // lds points at this transform's LDS region: element (n1, k2) lives at
 // lds[n1 * SN1 + k2 * SK2].  tw is the table of exp(-2 pi i j / (L * TS)).
-template <int L, int L1, bool INV, int TS, int SN1, int SK2>
-__device__ __forceinline__ void fft_2step(float2* v, int t, float2* lds, const float2* __restrict__ tw) {
+// Inter-step twiddles W^(t k2), k2 = 1 .. L2 - 1.  Read from the table one
+// by one (TWP = false), or (TWP = true) as products W^(t a) W^(t S b) of
+// table entries, k2 = a + S b with S^2 >= L2: S - 1 + L2/S - 1 reads instead
+// of L2 - 1 (10 instead of 31 for L2 = 32), so far fewer values are held in
+// registers while the reads are in flight, at about one extra rounding of a
+// complex product on the entries with a, b > 0.
+template <int L2>
+struct TwSplit {
+    static constexpr int S = L2 <= 4 ? L2 : (L2 <= 16 ? 4 : 8);
+    static_assert(L2 % S == 0, "twiddle split");
+};
+
+// SPLIT: the LDS exchange moves the real parts, then the imaginary parts,
+// through a float array of the same layout (half the LDS of a float2 one).
+template <int L, int L1, bool INV, int TS, int SN1, int SK2, bool TWP = false, bool SPLIT = false, class E = float2>
+__device__ __forceinline__ void fft_2step(float2* v, int t, E* lds, const float2* __restrict__ tw) {
+    static_assert(std::is_same<E, float>::value == SPLIT, "the LDS element type follows SPLIT");
     constexpr int L2 = L / L1;
     constexpr int RR = L2 / L1;
     static_assert(L1 * L2 == L && RR * L1 == L2, "bad split");
     Dft<L2, INV>::run(v);
+    if constexpr (TWP) {
+        constexpr int S = TwSplit<L2>::S, B = L2 / S;
+        float2 wa[S], wb[B];
+        wa[0] = wb[0] = make_float2(1.0f, 0.0f);
 #pragma unroll
-    for (int k2 = 1; k2 < L2; ++k2) {
-        float2 w = tw[(t * k2) * TS];
-        if (INV) w.y = -w.y;
-        v[k2] = cmul(v[k2], w);
+        for (int a = 1; a < S; ++a) wa[a] = tw[(t * a) * TS];
+#pragma unroll
+        for (int b = 1; b < B; ++b) wb[b] = tw[(t * S * b) * TS];
+#pragma unroll
+        for (int k2 = 1; k2 < L2; ++k2) {
+            const int a = k2 % S, b = k2 / S;
+            float2 w = (a == 0) ? wb[b] : (b == 0 ? wa[a] : cmul(wa[a], wb[b]));
+            if (INV) w.y = -w.y;
+            v[k2] = cmul(v[k2], w);
+        }
+    } else {
+#pragma unroll
+        for (int k2 = 1; k2 < L2; ++k2) {
+            float2 w = tw[(t * k2) * TS];
+            if (INV) w.y = -w.y;
+            v[k2] = cmul(v[k2], w);
+        }
     }
-    __syncthreads();
+    if constexpr (SPLIT) {
+        float re[L2];  // this thread's real parts after the exchange, RR groups of L1
+        __syncthreads();
 #pragma unroll
-    for (int k2 = 0; k2 < L2; ++k2) lds[t * SN1 + k2 * SK2] = v[k2];
-    __syncthreads();
+        for (int k2 = 0; k2 < L2; ++k2) lds[t * SN1 + k2 * SK2] = v[k2].x;
+        __syncthreads();
 #pragma unroll
-    for (int b = 0; b < RR; ++b) {
-        const int k2 = t + L1 * b;
-        float2 u[L1];
+        for (int b = 0; b < RR; ++b)
 #pragma unroll
-        for (int n1 = 0; n1 < L1; ++n1) u[n1] = lds[n1 * SN1 + k2 * SK2];
-        Dft<L1, INV>::run(u);
+            for (int n1 = 0; n1 < L1; ++n1) re[b * L1 + n1] = lds[n1 * SN1 + (t + L1 * b) * SK2];
+        __syncthreads();
 #pragma unroll
-        for (int k1 = 0; k1 < L1; ++k1) v[b + RR * k1] = u[k1];
+        for (int k2 = 0; k2 < L2; ++k2) lds[t * SN1 + k2 * SK2] = v[k2].y;
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < RR; ++b) {
+            const int k2 = t + L1 * b;
+            float2 u[L1];
+#pragma unroll
+            for (int n1 = 0; n1 < L1; ++n1) u[n1] = make_float2(re[b * L1 + n1], lds[n1 * SN1 + k2 * SK2]);
+            Dft<L1, INV>::run(u);
+#pragma unroll
+            for (int k1 = 0; k1 < L1; ++k1) v[b + RR * k1] = u[k1];
+        }
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int k2 = 0; k2 < L2; ++k2) lds[t * SN1 + k2 * SK2] = v[k2];
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < RR; ++b) {
+            const int k2 = t + L1 * b;
+            float2 u[L1];
+#pragma unroll
+            for (int n1 = 0; n1 < L1; ++n1) u[n1] = lds[n1 * SN1 + k2 * SK2];
+            Dft<L1, INV>::run(u);
+#pragma unroll
+            for (int k1 = 0; k1 < L1; ++k1) v[b + RR * k1] = u[k1];
+        }
     }
 }
 
@@ -305,11 +363,17 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned grid) {
 // MODE 1: forward transform, multiply by Khat(|k|)/N^3, inverse transform.
 // MODE 2: the input is already transformed along x: multiply, inverse.
 template <int N, class CS, int MODE, bool INV>
-__global__ __launch_bounds__(CS::C * CS::N1, 2) void k_fft_cols(
+__global__ __launch_bounds__(CS::C * CS::N1, MODE != 0 ? 4 : 2) void k_fft_cols(
     const float2* __restrict__ in, float2* __restrict__ out, const float2* __restrict__ tw,
     ColGeom g, MulArgs m) {
     constexpr int N1 = CS::N1, C = CS::C, N2 = N / N1;
-    __shared__ float2 lds[N1 * (N2 + 1) * C];
+    // The x pass (MODE 1, 2) holds a column through two transforms and the
+    // multiply: it exchanges real and imaginary parts separately (half the
+    // LDS, so more blocks share a compute unit) and forms its twiddles as
+    // products (fewer registers).
+    constexpr bool XP = MODE != 0;
+    using E = typename std::conditional<XP, float, float2>::type;
+    __shared__ E lds[N1 * (N2 + 1) * C];
     const int tid = threadIdx.x;
     const int c = tid % C, t = tid / C;
     const unsigned bid = xcd_tile(blockIdx.x, gridDim.x);
@@ -318,11 +382,11 @@ __global__ __launch_bounds__(CS::C * CS::N1, 2) void k_fft_cols(
     float2 v[N2];
 #pragma unroll
     for (int j = 0; j < N2; ++j) v[j] = in[base + (long long)(t + N1 * j) * g.row];
-    float2* col = lds + c;
-    if (MODE == 0) {
+    E* col = lds + c;
+    if constexpr (!XP) {
         fft_2step<N, N1, INV, 1, (N2 + 1) * C, C>(v, t, col, tw);
     } else {
-        if (MODE == 1) fft_2step<N, N1, false, 1, (N2 + 1) * C, C>(v, t, col, tw);
+        if (MODE == 1) fft_2step<N, N1, false, 1, (N2 + 1) * C, C, true, true>(v, t, col, tw);
         int my, mz;
         if (m.nyq) {
             my = tb * C + c;
@@ -338,7 +402,7 @@ __global__ __launch_bounds__(CS::C * CS::N1, 2) void k_fft_cols(
             const int sx = signed_freq(t + N1 * j, N);
             v[j] = cscale(v[j], khat_scaled(m.c2 * (float)(sx * sx + s2yz), m.ls));
         }
-        fft_2step<N, N1, true, 1, (N2 + 1) * C, C>(v, t, col, tw);
+        fft_2step<N, N1, true, 1, (N2 + 1) * C, C, true, true>(v, t, col, tw);
     }
     // The store addresses are recomputed here rather than kept from the loads
     // (kept, they are spilled to scratch in the fused passes at N = 1024).
