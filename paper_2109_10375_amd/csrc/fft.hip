@@ -367,13 +367,11 @@ __global__ __launch_bounds__(CS::C * CS::N1, MODE != 0 ? 4 : 2) void k_fft_cols(
     const float2* __restrict__ in, float2* __restrict__ out, const float2* __restrict__ tw,
     ColGeom g, MulArgs m) {
     constexpr int N1 = CS::N1, C = CS::C, N2 = N / N1;
-    // The x pass (MODE 1, 2) holds a column through two transforms and the
-    // multiply: it exchanges real and imaginary parts separately (half the
+    // A column pass exchanges real and imaginary parts separately (half the
     // LDS, so more blocks share a compute unit) and forms its twiddles as
-    // products (fewer registers).
-    constexpr bool XP = MODE != 0;
-    using E = typename std::conditional<XP, float, float2>::type;
-    __shared__ E lds[N1 * (N2 + 1) * C];
+    // products (fewer registers); the x pass, which holds a column through
+    // two transforms and the multiply, is held to four waves per SIMD.
+    __shared__ float lds[N1 * (N2 + 1) * C];
     const int tid = threadIdx.x;
     const int c = tid % C, t = tid / C;
     const unsigned bid = xcd_tile(blockIdx.x, gridDim.x);
@@ -382,9 +380,9 @@ __global__ __launch_bounds__(CS::C * CS::N1, MODE != 0 ? 4 : 2) void k_fft_cols(
     float2 v[N2];
 #pragma unroll
     for (int j = 0; j < N2; ++j) v[j] = in[base + (long long)(t + N1 * j) * g.row];
-    E* col = lds + c;
-    if constexpr (!XP) {
-        fft_2step<N, N1, INV, 1, (N2 + 1) * C, C>(v, t, col, tw);
+    float* col = lds + c;
+    if constexpr (MODE == 0) {
+        fft_2step<N, N1, INV, 1, (N2 + 1) * C, C, true, true>(v, t, col, tw);
     } else {
         if (MODE == 1) fft_2step<N, N1, false, 1, (N2 + 1) * C, C, true, true>(v, t, col, tw);
         int my, mz;
