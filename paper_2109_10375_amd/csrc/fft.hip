@@ -109,6 +109,17 @@ __device__ __forceinline__ float2 twc(float2 v, int e) {
     return make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
 }
 
+// W_N^k for k = t + S j (S | N, j < N / S): one table read W_N^t per thread
+// times the compile-time root W_{N/S}^j (one extra rounding of a complex
+// product instead of a table read per k).
+template <int N, int S>
+__device__ __forceinline__ float2 tw_split(float2 wt, int j) {
+    constexpr int R = N / S;
+    const int m = j % R;
+    if (m == 0) return wt;
+    return cmul(wt, make_float2(kRoots<R>.c[m], -kRoots<R>.s[m]));
+}
+
 // In-register DFT of R points, natural order in and out.
 template <int R>
 struct Split {  // R = A * B
@@ -420,7 +431,9 @@ __global__ __launch_bounds__(ZSc::ZL * ZSc::M1) void k_fft_z_r2c(
     const float2* __restrict__ tw, long long n_lines) {
     constexpr int M = N / 2, M1 = ZSc::M1, M2 = M / M1, ZL = ZSc::ZL;
     constexpr int LS = M1 * (M2 + 1);  // per-line LDS stride (>= M + 1)
-    __shared__ float2 lds[ZL * LS];
+    // real and imaginary parts go through LDS one after the other (half the
+    // LDS of a complex exchange, so more blocks share a compute unit)
+    __shared__ float lds[ZL * LS];
     const int tid = threadIdx.x;
     const int t = tid % M1, l = tid / M1;
     const long long line = (long long)blockIdx.x * ZL + l;
@@ -429,27 +442,39 @@ __global__ __launch_bounds__(ZSc::ZL * ZSc::M1) void k_fft_z_r2c(
     float2 v[M2];
 #pragma unroll
     for (int j = 0; j < M2; ++j) v[j] = live ? row[t + M1 * j] : make_float2(0.f, 0.f);
-    float2* mine = lds + l * LS;
-    fft_2step<M, M1, false, 2, M2 + 1, 1>(v, t, mine, tw);
+    float* mine = lds + l * LS;
+    fft_2step<M, M1, false, 2, M2 + 1, 1, true, true>(v, t, mine, tw);
+    // X[k] from Z[k] and Z[M-k]: the real parts first (a.x, b.x), then the
+    // imaginary parts (a.y, b.y)
+    float ax[M2], bx[M2], z0x = 0.0f;
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < M2; ++j) mine[t + M1 * j] = v[j];
+    for (int j = 0; j < M2; ++j) mine[t + M1 * j] = v[j].x;
     __syncthreads();
-    float2* orow = main_out + (live ? line : 0) * M;
 #pragma unroll
     for (int j = 0; j < M2; ++j) {
         const int k = t + M1 * j;
-        const float2 zk = mine[k];
-        const float2 zc = mine[(M - k) % M];
-        const float2 a = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
-        const float2 b = make_float2(0.5f * (zk.x - zc.x), 0.5f * (zk.y + zc.y));
-        const float2 wb = cmul(tw[k], b);
+        const float zk = mine[k], zc = mine[(M - k) % M];
+        ax[j] = 0.5f * (zk + zc);
+        bx[j] = 0.5f * (zk - zc);
+    }
+    if (t == 0) z0x = mine[0];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < M2; ++j) mine[t + M1 * j] = v[j].y;
+    __syncthreads();
+    float2* orow = main_out + (live ? line : 0) * M;
+    const float2 wt = tw[t];  // W_N^t; tw[k] = W_N^t W_{N/M1}^j
+#pragma unroll
+    for (int j = 0; j < M2; ++j) {
+        const int k = t + M1 * j;
+        const float zk = mine[k], zc = mine[(M - k) % M];
+        const float2 a = make_float2(ax[j], 0.5f * (zk - zc));
+        const float2 b = make_float2(bx[j], 0.5f * (zk + zc));
+        const float2 wb = cmul(tw_split<N, M1>(wt, j), b);
         if (live) orow[k] = make_float2(a.x + wb.y, a.y - wb.x);
     }
-    if (live && t == 0) {
-        const float2 z0 = mine[0];
-        nyq_out[line] = make_float2(z0.x - z0.y, 0.0f);
-    }
+    if (live && t == 0) nyq_out[line] = make_float2(z0x - mine[0], 0.0f);
 }
 
 // z pass, complex to real (unnormalised inverse):
@@ -461,36 +486,52 @@ __global__ __launch_bounds__(ZSc::ZL * ZSc::M1) void k_fft_z_c2r(
     const float2* __restrict__ tw, long long n_lines) {
     constexpr int M = N / 2, M1 = ZSc::M1, M2 = M / M1, ZL = ZSc::ZL;
     constexpr int LS = M1 * (M2 + 1);
-    __shared__ float2 lds[ZL * LS];
+    // real and imaginary parts go through LDS one after the other
+    __shared__ float lds[ZL * LS];
     const int tid = threadIdx.x;
     const int t = tid % M1, l = tid / M1;
     const long long line = (long long)blockIdx.x * ZL + l;
     const bool live = line < n_lines;
     const float2* irow = main_in + (live ? line : 0) * M;
-    float2* mine = lds + l * LS;
+    float* mine = lds + l * LS;
     // all loads in flight before the LDS writes (a dead line reads line 0 and
     // is never stored)
     float2 in[M2];
 #pragma unroll
     for (int j = 0; j < M2; ++j) in[j] = irow[t + M1 * j];
     const float2 nq = nyq_in[live ? line : 0];
+    // X[k] and X[M-k]: the real parts first (e.x, d.x), then the imaginary
+    // parts (e.y, d.y)
+    float ex[M2], dx[M2];
 #pragma unroll
-    for (int j = 0; j < M2; ++j) mine[t + M1 * j] = in[j];
-    if (t == 0) mine[M] = nq;
+    for (int j = 0; j < M2; ++j) mine[t + M1 * j] = in[j].x;
+    if (t == 0) mine[M] = nq.x;
     __syncthreads();
-    float2 v[M2];
 #pragma unroll
     for (int j = 0; j < M2; ++j) {
         const int k = t + M1 * j;
-        const float2 xk = mine[k];
-        const float2 xm = mine[M - k];
-        const float2 e = make_float2(xk.x + xm.x, xk.y - xm.y);   // X[k] + conj X[M-k]
-        const float2 d = make_float2(xk.x - xm.x, xk.y + xm.y);   // X[k] - conj X[M-k]
-        const float2 w = tw[k];
+        const float xk = mine[k], xm = mine[M - k];
+        ex[j] = xk + xm;
+        dx[j] = xk - xm;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < M2; ++j) mine[t + M1 * j] = in[j].y;
+    if (t == 0) mine[M] = nq.y;
+    __syncthreads();
+    float2 v[M2];
+    const float2 wt = tw[t];  // W_N^t; tw[k] = W_N^t W_{N/M1}^j
+#pragma unroll
+    for (int j = 0; j < M2; ++j) {
+        const int k = t + M1 * j;
+        const float xk = mine[k], xm = mine[M - k];
+        const float2 e = make_float2(ex[j], xk - xm);              // X[k] + conj X[M-k]
+        const float2 d = make_float2(dx[j], xk + xm);              // X[k] - conj X[M-k]
+        const float2 w = tw_split<N, M1>(wt, j);
         const float2 o = cmul(d, make_float2(w.x, -w.y));          // * W_N^-k
         v[j] = make_float2(e.x - o.y, e.y + o.x);                  // e + i o
     }
-    fft_2step<M, M1, true, 2, M2 + 1, 1>(v, t, mine, tw);
+    fft_2step<M, M1, true, 2, M2 + 1, 1, true, true>(v, t, mine, tw);
     if (live) {
         float2* orow = reinterpret_cast<float2*>(dst + line * N);
 #pragma unroll
