@@ -9,9 +9,10 @@
 // and every pass is stable, so equal intensities keep ascending cell index.
 //
 // Each pass ("onesweep"): a block takes the next tile (16384 keys on large
-// grids, 4096 on small ones) from a ticket counter, ranks its keys by digit with 64-lane ballots (the lanes that share a
-// digit find each other with 8 ballots; the lowest of them bumps the wave's LDS
-// counter), publishes its per-digit counts for later tiles and looks back over
+// grids, 4096 on small ones) from a ticket counter, ranks its keys by digit
+// within each wave (the lanes that share a digit find each other through a
+// per-digit LDS mask, or in the last pass with 8 ballots; the lowest of them
+// bumps the wave's LDS counter), publishes its per-digit counts for later tiles and looks back over
 // earlier tiles' published counts (decoupled look-back) to find where its
 // digits start globally, then writes its keys digit by digit through LDS so
 // that each digit's run is stored contiguously.  Tiles only wait on tiles that
@@ -266,6 +267,13 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     // spare counter for lanes past the end of the last tile)
     constexpr int kRow = LAST ? 257 : 256;
     __shared__ unsigned short wcnt[kWaves][kRow];
+    // Peer matching in the passes whose digits are spread: per wave and digit
+    // a 64-bit mask that the lanes of one key round OR their bits into, read
+    // back and clear (entry 256 takes the lanes past the end of the last
+    // tile).  The last pass, whose top digit takes few values (so the atomics
+    // of one instruction would mostly hit one address), matches by ballots.
+    constexpr bool kPeerLds = !LAST;
+    __shared__ unsigned long long pmask[kPeerLds ? kWaves : 1][kPeerLds ? 257 : 1];
     __shared__ unsigned loff[256];                // tile-local start of each digit
     __shared__ unsigned gbase[256];               // global start of each digit's run of this tile
     __shared__ unsigned scan_sh[4];
@@ -289,6 +297,8 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     };
     if (tid == 0) s_tile = atomicAdd(&ctrl->tickets[pass], 1u);
     for (int i = tid; i < kWaves * kRow; i += kThreads) (&wcnt[0][0])[i] = 0;
+    if (kPeerLds)
+        for (int i = tid; i < kWaves * 257; i += kThreads) (&pmask[0][0])[i] = 0ull;
     __syncthreads();
     const unsigned tile = s_tile;
     const long long tile_base = (long long)tile * kTile;
@@ -359,17 +369,31 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     for (int j = 0; j < kKeysPerThread; ++j) {
         const bool ok = (wbase + 64 * j + lane) < n;
         const unsigned d = (key[j] >> shift) & 255u;
-        const unsigned long long ok_mask = __ballot(ok);
-        // lanes whose digit equals this lane's, bit by bit on 32-bit halves
-        // (each step is one 3-input bit operation per half)
-        unsigned plo = (unsigned)ok_mask, phi = (unsigned)(ok_mask >> 32);
-        if (LAST) {
-            // The top digit takes few values, so peer groups are large.  The
-            // all-ones-where-set word is a signed one-bit extract of the key,
-            // and no branch: every peer writes the same new count (lanes past
-            // the end of the last tile use the spare counter).  (Measured
-            // faster here, 5.0 -> 4.6 ms at 2^30 keys; slower in the other
-            // passes, whose digits are spread.)
+        if constexpr (kPeerLds) {
+            // the lanes with this lane's digit: one LDS atomic OR per lane, one
+            // read, one clear (a wave's LDS operations complete in order)
+            const unsigned dd = ok ? d : 256u;
+            atomicOr(&pmask[wave][dd], 1ull << lane);
+            const unsigned long long peers = pmask[wave][dd];
+            pmask[wave][dd] = 0ull;
+            unsigned r = 0;
+            if (ok) {
+                const unsigned before = (unsigned)__popcll(peers & lt);
+                const unsigned cnt = (unsigned)__popcll(peers);
+                const unsigned old = wcnt[wave][d];
+                r = old + before;
+                if (before == 0) wcnt[wave][d] = (unsigned short)(old + cnt);  // lowest peer updates
+            }
+            lrank[j] = r;
+        } else {
+            // The top digit takes few values, so peer groups are large: lanes
+            // whose digit equals this lane's, bit by bit on 32-bit halves (the
+            // all-ones-where-set word a signed one-bit extract of the key, each
+            // step one 3-input bit operation per half), and no branch: every
+            // peer writes the same new count (lanes past the end of the last
+            // tile use the spare counter).
+            const unsigned long long ok_mask = __ballot(ok);
+            unsigned plo = (unsigned)ok_mask, phi = (unsigned)(ok_mask >> 32);
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 const unsigned ext = (unsigned)__builtin_amdgcn_sbfe((int)key[j], shift + b, 1);
@@ -384,25 +408,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
             const unsigned old = wcnt[wave][dd];
             lrank[j] = old + before;
             wcnt[wave][dd] = (unsigned short)(old + cnt);
-            continue;
         }
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const unsigned ext = 0u - ((d >> b) & 1u);  // all ones where the bit is set
-            const unsigned long long m = __ballot(ext != 0u);
-            plo &= ~(ext ^ (unsigned)m);
-            phi &= ~(ext ^ (unsigned)(m >> 32));
-        }
-        const unsigned long long peers = ((unsigned long long)phi << 32) | plo;
-        unsigned r = 0;
-        if (ok) {
-            const unsigned before = (unsigned)__popcll(peers & lt);
-            const unsigned cnt = (unsigned)__popcll(peers);
-            const unsigned old = wcnt[wave][d];
-            r = old + before;
-            if (before == 0) wcnt[wave][d] = (unsigned short)(old + cnt);  // lowest peer updates
-        }
-        lrank[j] = r;
     }
     __syncthreads();
 
