@@ -105,6 +105,13 @@ struct Ctrl {
     int qmin;                   // exponent of the smallest weight ulp (w = m 2^q)
     int wide;                   // 1 when the total needs more than 64 bits
     unsigned long long total_lo, total_hi;  // exact sum of w 2^-qmin
+    // Radix passes 0-2 split their input into 8 segments (rank.hip): counts
+    // of the pass's digit per segment, turned by the offsets kernel into
+    // where the run of digit d from segment s starts in the output.
+    unsigned segcnt[3][8][256];
+    unsigned seg_start[4][9];   // pass k: first element of segment s (s = 8: n)
+    unsigned seg_tile0[4][9];   // pass k: look-back id of segment s's first tile (s = 8: the pass's tiles)
+    unsigned seg_ticket[4][8];  // pass k: next tile of segment s
 };
 
 // Decoupled look-back over 30-bit counts with a 2-bit flag (aggregate or

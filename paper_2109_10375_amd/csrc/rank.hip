@@ -73,21 +73,27 @@ __device__ __forceinline__ unsigned digit_excl_scan(unsigned v, unsigned* sh /* 
     return x + add - v;
 }
 
-// Clears the control block's histograms' look-back companion region, counts
-// the four digit histograms of the keys (read once, 16 per thread in flight),
-// and flags NaN intensities.  n is a multiple of 4.
+// Clears pass 0's look-back region, counts the digits of the keys per
+// segment of each pass's input (keys read once, 16 per thread in flight) and
+// flags NaN intensities.  n is a multiple of 4.  Segments: pass 0's are
+// ranges of tps input tiles (tile / tps = (tile * seg_mul) >> 32); the input
+// of pass k = 1, 2 is ordered by digit k-1, and its segment s holds the keys
+// whose digit k-1 has top three bits s; the last pass has one segment.  The
+// block's counts of passes 0-2 go to part[block] (or, when part is null,
+// straight into the control block), the top digit's into the control block.
 __global__ __launch_bounds__(kHistThreads) void k_hist(const float* __restrict__ J, long long n, Ctrl* ctrl,
-                                                       unsigned* __restrict__ lb0, long long lb_words) {
-    __shared__ unsigned h[kHistWaves][4][256];
+                                                       unsigned* __restrict__ lb0, long long lb_words,
+                                                       unsigned* __restrict__ part, int tile_shift,
+                                                       unsigned long long seg_mul) {
+    __shared__ unsigned h[3][8][256];
     // The top digit (sign and exponent) takes a handful of values, so one
     // LDS word per value would take the atomics of most lanes at once: it is
     // counted per lane instead, in 16-bit halves (lanes 2k and 2k+1 share a
     // word, the block's waves share the words: at most kHistWaves * 16 keys
     // per round per half, which the host keeps below 2^16).
     __shared__ unsigned top[256][32];
-    const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    for (int i = threadIdx.x; i < kHistWaves * 4 * 256; i += kHistThreads) (&h[0][0][0])[i] = 0;
+    for (int i = threadIdx.x; i < 3 * 8 * 256; i += kHistThreads) (&h[0][0][0])[i] = 0;
     for (int i = threadIdx.x; i < 256 * 32; i += kHistThreads) (&top[0][0])[i] = 0;
     for (long long i = (long long)blockIdx.x * kHistThreads + threadIdx.x; i < lb_words;
          i += (long long)gridDim.x * kHistThreads)
@@ -107,16 +113,21 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const float* __restrict__
         }
 #pragma unroll
         for (int k = 0; k < kV; ++k) {
-            const bool live = base + k * kHistThreads + threadIdx.x < n4;
+            const long long i = base + k * kHistThreads + threadIdx.x;
+            const bool live = i < n4;
+            const unsigned tile = (unsigned)((4 * i) >> tile_shift);
+            unsigned s0 = (unsigned)(((unsigned long long)tile * seg_mul) >> 32);  // < 2^48 before the shift
+            s0 = s0 < 8u ? s0 : 7u;
             const float f[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const unsigned key = desc_key(f[e]);
                 if (live) {
                     nan |= is_nan_bits(__float_as_uint(f[e]));
-                    atomicAdd(&h[wave][0][key & 255u], 1u);
-                    atomicAdd(&h[wave][1][(key >> 8) & 255u], 1u);
-                    atomicAdd(&h[wave][2][(key >> 16) & 255u], 1u);
+                    const unsigned d0 = key & 255u, d1 = (key >> 8) & 255u;
+                    atomicAdd(&h[0][s0][d0], 1u);
+                    atomicAdd(&h[1][d0 >> 5][d1], 1u);
+                    atomicAdd(&h[2][d1 >> 5][(key >> 16) & 255u], 1u);
                     atomicAdd(&top[key >> 24][lane >> 1], (lane & 1) ? 65536u : 1u);
                 }
             }
@@ -130,15 +141,22 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const float* __restrict__
             const unsigned x = top[d][j];
             c += (x & 0xffffu) + (x >> 16);
         }
-        h[0][3][d] += c;
+        if (c) atomicAdd(&ctrl->hist[3][d], c);
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < 4 * 256; i += kHistThreads) {
-        unsigned s = 0;
-#pragma unroll
-        for (int w = 0; w < kHistWaves; ++w) s += (&h[w][0][0])[i];
-        if (s) atomicAdd(&ctrl->hist[0][0] + i, s);
+    for (int i = threadIdx.x; i < 3 * 8 * 256; i += kHistThreads) {
+        const unsigned c = (&h[0][0][0])[i];
+        if (part) part[(long long)blockIdx.x * (3 * 8 * 256) + i] = c;
+        else if (c) atomicAdd(&ctrl->segcnt[0][0][0] + i, c);
     }
+}
+
+// Sums the blocks' segment counts: block (x, y) adds rows y, y + gridDim.y, ...
+// of columns 256 x .. 256 x + 255 into the control block.
+__global__ __launch_bounds__(256) void k_seg_reduce(const unsigned* __restrict__ part, long long rows, Ctrl* ctrl) {
+    const int col = blockIdx.x * 256 + threadIdx.x;  // < 3 * 8 * 256
+    unsigned c = 0;
+    for (long long r = blockIdx.y; r < rows; r += gridDim.y) c += part[r * (3 * 8 * 256) + col];
+    if (c) atomicAdd(&ctrl->segcnt[0][0][0] + col, c);
 }
 
 __global__ void k_ctrl_init(Ctrl* ctrl, unsigned* sticky) {
@@ -151,14 +169,46 @@ __global__ void k_ctrl_init(Ctrl* ctrl, unsigned* sticky) {
     }
 }
 
-// Exclusive prefix of each digit histogram: where each digit's run starts.
-__global__ __launch_bounds__(256) void k_digit_offsets(Ctrl* ctrl) {
+// Exclusive prefix of each digit histogram (where each digit's run starts),
+// the start of each segment's runs (passes 0-2: the digit's start plus the
+// counts of the earlier segments), and each pass's segments: where they start
+// and the look-back id of their first tile (tiles of `tile` keys from the
+// segment's start; pass 0's segments are ranges of tps tiles).
+__global__ __launch_bounds__(256) void k_digit_offsets(Ctrl* ctrl, long long n, int tile, unsigned tps) {
     __shared__ unsigned sh[4];
-    for (int d = 0; d < 4; ++d) {
-        const unsigned v = ctrl->hist[d][threadIdx.x];
-        const unsigned ex = digit_excl_scan(v, sh);
-        ctrl->digit_off[d][threadIdx.x] = ex;
-        __syncthreads();
+    const int d = threadIdx.x;
+    for (int k = 0; k < 3; ++k) {
+        unsigned tot = 0;
+        for (int s = 0; s < 8; ++s) tot += ctrl->segcnt[k][s][d];
+        ctrl->hist[k][d] = tot;
+        const unsigned ex = digit_excl_scan(tot, sh);
+        ctrl->digit_off[k][d] = ex;
+        unsigned run = ex;
+        for (int s = 0; s < 8; ++s) {
+            const unsigned c = ctrl->segcnt[k][s][d];
+            ctrl->segcnt[k][s][d] = run;
+            run += c;
+        }
+        __syncthreads();  // scan_sh is reused
+    }
+    ctrl->digit_off[3][d] = digit_excl_scan(ctrl->hist[3][d], sh);
+    __syncthreads();  // the digit starts are read below by other threads
+    if (d < 4) {
+        const int k = d;
+        unsigned st[9];
+        for (int s = 0; s <= 8; ++s) {
+            long long v;
+            if (k == 0) v = std::min<long long>((long long)s * tps * tile, n);
+            else if (k < 3) v = s == 8 ? n : ctrl->digit_off[k - 1][32 * s];
+            else v = s == 0 ? 0 : n;
+            st[s] = (unsigned)v;
+        }
+        unsigned t0 = 0;
+        for (int s = 0; s <= 8; ++s) {
+            ctrl->seg_start[k][s] = st[s];
+            ctrl->seg_tile0[k][s] = t0;
+            if (s < 8) t0 += (st[s + 1] - st[s] + (unsigned)tile - 1) / (unsigned)tile;
+        }
     }
 }
 
@@ -197,22 +247,23 @@ template <int kThreads, bool CARRY, class Row>
 __device__ __forceinline__ void last_pass_stores(const unsigned* key, const unsigned* val, const float* wt,
                                                  const unsigned* lrank, const Row& wrow, const unsigned* loff,
                                                  const unsigned* gbase, unsigned* stage, unsigned* __restrict__ vals_out,
-                                                 float* __restrict__ w_out, long long tile_base, long long n, int shift) {
+                                                 float* __restrict__ w_out, long long tile_base, long long tend,
+                                                 long long n, int shift) {
     constexpr int kTile = kThreads * kKeysPerThread;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long wbase = tile_base + (long long)wave * (64 * kKeysPerThread);
-    const bool full = tile_base + kTile <= n;
+    const bool full = tile_base + kTile <= tend;
     unsigned lpos[kKeysPerThread];
 #pragma unroll
     for (int j = 0; j < kKeysPerThread; ++j) {
-        const bool ok = (wbase + 64 * j + lane) < n;
+        const bool ok = (wbase + 64 * j + lane) < tend;
         const unsigned dd = (key[j] >> shift) & 255u;
         const unsigned p = loff[dd] + wrow[dd] + lrank[j];
         lpos[j] = (ok && p < (unsigned)kTile) ? p : (unsigned)kTile + lane;  // p < kTile for consistent counts
         stage[lpos[j]] = key[j];
     }
     __syncthreads();
-    const long long valid_ll = n - tile_base;
+    const long long valid_ll = tend - tile_base;
     const int valid = valid_ll < kTile ? (int)valid_ll : kTile;
     const unsigned last = (unsigned)(n - 1);
     unsigned dst[kKeysPerThread];
@@ -253,6 +304,17 @@ __device__ __forceinline__ void last_pass_stores(const unsigned* key, const unsi
 // come from J and the index is the position.  LAST: only the values (and
 // weights) are written.  CARRY: weights travel with the keys; pass 0 also
 // checks them and stores the smallest ulp exponent of each tile in qtile[tile].
+//
+// The input is split into 8 segments, each cut into tiles from its start with
+// a ticket counter and a look-back chain of its own; the runs a segment's keys
+// form start at offsets the histogram kernel counted.  A block takes a tile of
+// segment blockIdx % 8 and of the next segments once that one is used up, so
+// consecutive tiles, whose digit runs meet inside cache lines, are written
+// from the same XCD's L2 (blocks are dealt to the 8 XCDs round robin) while
+// there is work for it.  A tile waits only on earlier tiles of its segment,
+// which took earlier tickets and are already running, so every wait ends.
+// The grid has a block for every look-back id of every pass (tiles + 8);
+// block b clears id b's entries of the next passes.
 template <int kThreads, bool FIRST, bool LAST, bool CARRY, int KIN = 4, int KOUT = 4>
 __global__ __launch_bounds__(kThreads) void k_onesweep(
     const float* __restrict__ J, const void* __restrict__ keys_in_v, const unsigned* __restrict__ vals_in,
@@ -262,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     constexpr int kWaves = kThreads / 64;
     constexpr int kTile = kThreads * kKeysPerThread;
     static_assert(kThreads >= 256 && kThreads % 64 == 0 && kTile <= 65535, "tile geometry");
-    __shared__ unsigned s_tile;
+    __shared__ unsigned s_seg, s_j;
     // per-wave digit counts, then wave offsets (the last pass: entry 256 is a
     // spare counter for lanes past the end of the last tile)
     constexpr int kRow = LAST ? 257 : 256;
@@ -295,20 +357,38 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
         else if (KOUT == 2) reinterpret_cast<unsigned short*>(keys_out_v)[i] = (unsigned short)(k >> 16);
         else reinterpret_cast<unsigned char*>(keys_out_v)[i] = (unsigned char)(k >> 24);
     };
-    if (tid == 0) s_tile = atomicAdd(&ctrl->tickets[pass], 1u);
+    if (tid == 0) {
+        unsigned seg = 8u, jj = 0u;
+        for (int t = 0; t < 8; ++t) {
+            const unsigned sg = (blockIdx.x + (unsigned)t) & 7u;
+            const unsigned cnt = ctrl->seg_tile0[pass][sg + 1] - ctrl->seg_tile0[pass][sg];
+            if (cnt == 0u) continue;
+            const unsigned j = atomicAdd(&ctrl->seg_ticket[pass][sg], 1u);
+            if (j < cnt) {
+                seg = sg;
+                jj = j;
+                break;
+            }
+        }
+        s_seg = seg;
+        s_j = jj;
+    }
     for (int i = tid; i < kWaves * kRow; i += kThreads) (&wcnt[0][0])[i] = 0;
     if (kPeerLds)
         for (int i = tid; i < kWaves * 257; i += kThreads) (&pmask[0][0])[i] = 0ull;
-    __syncthreads();
-    const unsigned tile = s_tile;
-    const long long tile_base = (long long)tile * kTile;
-    const int shift = 8 * pass;
-
-    // The next passes' look-back entries for this tile start cleared.
+    // The next passes' look-back entries start cleared.
     if (tid < 256) {
-        if (lb_next) lb_next[(long long)tile * 256 + tid] = 0u;
-        if (lb_next2) lb_next2[(long long)tile * 256 + tid] = 0u;
+        if (lb_next) lb_next[(long long)blockIdx.x * 256 + tid] = 0u;
+        if (lb_next2) lb_next2[(long long)blockIdx.x * 256 + tid] = 0u;
     }
+    __syncthreads();
+    const unsigned seg = s_seg, seg_j = s_j;
+    if (seg >= 8u) return;  // every tile is taken
+    const unsigned tile = ctrl->seg_tile0[pass][seg] + seg_j;  // look-back id
+    const long long tile_base = (long long)ctrl->seg_start[pass][seg] + (long long)seg_j * kTile;
+    const long long seg_end = ctrl->seg_start[pass][seg + 1];
+    const long long tend = tile_base + kTile < seg_end ? tile_base + kTile : seg_end;
+    const int shift = 8 * pass;
 
     unsigned key[kKeysPerThread], val[kKeysPerThread], lrank[kKeysPerThread];
     float wt[kKeysPerThread];
@@ -320,7 +400,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     // loads at one lane offset plus constant strides; the last tile clamps
     // its positions, and its out-of-range lanes are masked after.
     const unsigned lane0 = (unsigned)wbase + (unsigned)lane;
-    if (tile_base + kTile <= n) {
+    if (tile_base + kTile <= tend) {
 #pragma unroll
         for (int j = 0; j < kKeysPerThread; ++j) {
             const unsigned pos = lane0 + 64u * j;
@@ -334,7 +414,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
             if (CARRY) wt[j] = w_in[pos];
         }
     } else {
-        const unsigned last = (unsigned)(n - 1);
+        const unsigned last = (unsigned)(tend - 1);
 #pragma unroll
         for (int j = 0; j < kKeysPerThread; ++j) {
             const unsigned pos = lane0 + 64u * j;
@@ -351,7 +431,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     }
 #pragma unroll
     for (int j = 0; j < kKeysPerThread; ++j) {
-        const bool ok = wbase + 64 * j + lane < n;
+        const bool ok = wbase + 64 * j + lane < tend;
         if (FIRST) key[j] = desc_key(__uint_as_float(key[j]));
         if (!ok) key[j] = 0xffffffffu;
         if (CARRY && FIRST && ok) {
@@ -367,7 +447,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
     for (int j = 0; j < kKeysPerThread; ++j) {
-        const bool ok = (wbase + 64 * j + lane) < n;
+        const bool ok = (wbase + 64 * j + lane) < tend;
         const unsigned d = (key[j] >> shift) & 255u;
         if constexpr (kPeerLds) {
             // the lanes with this lane's digit: one LDS atomic OR per lane, one
@@ -425,14 +505,15 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
         }
         tcnt = run;
         unsigned* me = lb + (long long)tile * 256 + d;
-        if (tile == 0) {
+        const unsigned seg_base = LAST ? ctrl->digit_off[3][d] : ctrl->segcnt[pass][seg][d];
+        if (seg_j == 0) {
             st_release(me, kFlagPre | tcnt);
-            gbase[d] = ctrl->digit_off[pass][d];
+            gbase[d] = seg_base;
         } else {
             st_release(me, kFlagAgg | tcnt);
-            const unsigned excl = lb_walk(lb, (long long)tile, d, 0);
+            const unsigned excl = lb_walk(lb, (long long)tile, d, (long long)ctrl->seg_tile0[pass][seg]);
             st_release(me, kFlagPre | (excl + tcnt));
-            gbase[d] = ctrl->digit_off[pass][d] + excl;
+            gbase[d] = seg_base + excl;
         }
     }
     const unsigned lo = digit_excl_scan(tcnt, scan_sh);
@@ -466,20 +547,20 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     // digit, and keeps it for the indices and weights staged after it.
     if constexpr (LAST) {
         last_pass_stores<kThreads, CARRY>(key, val, wt, lrank, wcnt[wave], loff, gbase, stage, vals_out, w_out,
-                                          tile_base, n, shift);
+                                          tile_base, tend, n, shift);
         return;
     }
     unsigned lpos[kKeysPerThread];
 #pragma unroll
     for (int j = 0; j < kKeysPerThread; ++j) {
-        const bool ok = (wbase + 64 * j + lane) < n;
+        const bool ok = (wbase + 64 * j + lane) < tend;
         const unsigned dd = (key[j] >> shift) & 255u;
         const unsigned p = ok ? loff[dd] + wcnt[wave][dd] + lrank[j] : 0xffffffffu;
         lpos[j] = p < (unsigned)kTile ? p : 0xffffffffu;  // out of range is unreachable for consistent counts
         if (lpos[j] != 0xffffffffu) stage[p] = key[j];
     }
     __syncthreads();
-    const long long valid_ll = n - tile_base;
+    const long long valid_ll = tend - tile_base;
     const int valid = valid_ll < kTile ? (int)valid_ll : kTile;
     unsigned dst[kKeysPerThread];
 #pragma unroll
@@ -535,7 +616,9 @@ template <int T>
 static void launch_passes(const amber_plan_s* p, const float* d_J, const float* d_w, hipStream_t s, int carry,
                           unsigned* const* keys, unsigned* const* vals, float* const* wts, unsigned* const* lb,
                           uint32_t* final_vals, int* qtile, Ctrl* ctrl, long long n, long long n_tiles) {
-    const dim3 grid((unsigned)n_tiles), blk(T);
+    // a block for every look-back id of every pass: segments cut at most 8
+    // more tiles than n_tiles (pass 0's exactly n_tiles)
+    const dim3 grid((unsigned)(n_tiles + 8)), blk(T);
     // pass 0: J, w -> buffers 1; pass 1: 1 -> 0; pass 2: 0 -> 1; pass 3: 1 -> 0 (values, weights)
     if (carry) {
         AMBER_LAUNCH(p, "rank_pass0", (k_onesweep<T, true, false, true>), grid, blk, s, d_J, nullptr, nullptr, d_w,
@@ -580,8 +663,23 @@ int rank_sort(const amber_plan_s* p, const float* d_J, const float* d_w, unsigne
     // the histogram's per-lane top-digit counters are 16 bits wide
     const long long hist_step = (long long)hist_blocks * kHistThreads * 4;
     if ((long long)kHistWaves * 16 * ((n / 4 + hist_step - 1) / hist_step) > 65535) return AMBER_E_SIZE;
-    AMBER_LAUNCH(p, "rank_hist", k_hist, dim3(hist_blocks), dim3(kHistThreads), s, d_J, n, ctrl, lb[0], n_tiles * 256);
-    AMBER_LAUNCH(p, "rank_digit_offsets", k_digit_offsets, dim3(1), dim3(256), s, ctrl);
+    // pass 0's segments: ranges of tps tiles; tile / tps = (tile * seg_mul) >> 32
+    // exactly for tile < 2^16 (seg_mul <= 2^32)
+    const unsigned tps = (unsigned)((n_tiles + 7) / 8);
+    const unsigned long long seg_mul = ((1ULL << 32) + tps - 1) / tps;
+    int tile_shift = 0;
+    while ((1LL << tile_shift) < tile) ++tile_shift;
+    if (n_tiles > 65536) return AMBER_E_SIZE;
+    // The blocks' segment counts go through the first key buffer (free until
+    // pass 1) where it holds them, else straight into the control block.
+    constexpr long long kSegWords = 3 * 8 * 256;
+    unsigned* part = (long long)hist_blocks * kSegWords <= n ? keys[0] : nullptr;
+    AMBER_LAUNCH(p, "rank_hist", k_hist, dim3(hist_blocks), dim3(kHistThreads), s, d_J, n, ctrl, lb[0], n_tiles * 256,
+                 part, tile_shift, seg_mul);
+    if (part)
+        AMBER_LAUNCH(p, "rank_seg_reduce", k_seg_reduce, dim3((unsigned)(kSegWords / 256), std::min(64u, hist_blocks)),
+                     dim3(256), s, part, (long long)hist_blocks, ctrl);
+    AMBER_LAUNCH(p, "rank_digit_offsets", k_digit_offsets, dim3(1), dim3(256), s, ctrl, n, (int)tile, tps);
     uint32_t* final_vals = d_perm_out ? d_perm_out : vals[0];
     // the per-tile ulp exponents of pass 0 live in the third look-back region
     // until the last pass clears it
