@@ -247,24 +247,23 @@ template <int kThreads, bool CARRY, class Row>
 __device__ __forceinline__ void last_pass_stores(const unsigned* key, const unsigned* val, const float* wt,
                                                  const unsigned* lrank, const Row& wrow, const unsigned* loff,
                                                  const unsigned* gbase, unsigned* stage, unsigned* __restrict__ vals_out,
-                                                 float* __restrict__ w_out, long long tile_base, long long tend,
+                                                 float* __restrict__ w_out, unsigned tile_base, unsigned tend,
                                                  long long n, int shift) {
     constexpr int kTile = kThreads * kKeysPerThread;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const long long wbase = tile_base + (long long)wave * (64 * kKeysPerThread);
+    const unsigned wbase = tile_base + (unsigned)wave * (64 * kKeysPerThread);
     const bool full = tile_base + kTile <= tend;
     unsigned lpos[kKeysPerThread];
 #pragma unroll
     for (int j = 0; j < kKeysPerThread; ++j) {
-        const bool ok = (wbase + 64 * j + lane) < tend;
+        const bool ok = (wbase + 64u * j + lane) < tend;
         const unsigned dd = (key[j] >> shift) & 255u;
         const unsigned p = loff[dd] + wrow[dd] + lrank[j];
         lpos[j] = (ok && p < (unsigned)kTile) ? p : (unsigned)kTile + lane;  // p < kTile for consistent counts
         stage[lpos[j]] = key[j];
     }
     __syncthreads();
-    const long long valid_ll = tend - tile_base;
-    const int valid = valid_ll < kTile ? (int)valid_ll : kTile;
+    const int valid = (int)(tend - tile_base);  // <= kTile
     const unsigned last = (unsigned)(n - 1);
     unsigned dst[kKeysPerThread];
 #pragma unroll
@@ -385,21 +384,22 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     const unsigned seg = s_seg, seg_j = s_j;
     if (seg >= 8u) return;  // every tile is taken
     const unsigned tile = ctrl->seg_tile0[pass][seg] + seg_j;  // look-back id
-    const long long tile_base = (long long)ctrl->seg_start[pass][seg] + (long long)seg_j * kTile;
-    const long long seg_end = ctrl->seg_start[pass][seg + 1];
-    const long long tend = tile_base + kTile < seg_end ? tile_base + kTile : seg_end;
+    // element positions fit in 32 bits (n <= 2^30)
+    const unsigned tile_base = ctrl->seg_start[pass][seg] + seg_j * (unsigned)kTile;
+    const unsigned seg_end = ctrl->seg_start[pass][seg + 1];
+    const unsigned tend = tile_base + kTile < seg_end ? tile_base + kTile : seg_end;
     const int shift = 8 * pass;
 
     unsigned key[kKeysPerThread], val[kKeysPerThread], lrank[kKeysPerThread];
     float wt[kKeysPerThread];
     bool bad_w = false;
     int qmin = 0x7fffffff;
-    const long long wbase = tile_base + (long long)wave * (64 * kKeysPerThread);
+    const unsigned wbase = tile_base + (unsigned)wave * (64 * kKeysPerThread);
     // All loads first (no branch around a load, so they are all in flight
     // together).  Element indices fit in 32 bits (n <= 2^30): a full tile
     // loads at one lane offset plus constant strides; the last tile clamps
     // its positions, and its out-of-range lanes are masked after.
-    const unsigned lane0 = (unsigned)wbase + (unsigned)lane;
+    const unsigned lane0 = wbase + (unsigned)lane;
     if (tile_base + kTile <= tend) {
 #pragma unroll
         for (int j = 0; j < kKeysPerThread; ++j) {
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
             if (CARRY) wt[j] = w_in[pos];
         }
     } else {
-        const unsigned last = (unsigned)(tend - 1);
+        const unsigned last = tend - 1u;
 #pragma unroll
         for (int j = 0; j < kKeysPerThread; ++j) {
             const unsigned pos = lane0 + 64u * j;
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     }
 #pragma unroll
     for (int j = 0; j < kKeysPerThread; ++j) {
-        const bool ok = wbase + 64 * j + lane < tend;
+        const bool ok = lane0 + 64u * j < tend;
         if (FIRST) key[j] = desc_key(__uint_as_float(key[j]));
         if (!ok) key[j] = 0xffffffffu;
         if (CARRY && FIRST && ok) {
@@ -447,7 +447,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
     for (int j = 0; j < kKeysPerThread; ++j) {
-        const bool ok = (wbase + 64 * j + lane) < tend;
+        const bool ok = lane0 + 64u * j < tend;
         const unsigned d = (key[j] >> shift) & 255u;
         if constexpr (kPeerLds) {
             // the lanes with this lane's digit: one LDS atomic OR per lane, one
@@ -553,15 +553,14 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     unsigned lpos[kKeysPerThread];
 #pragma unroll
     for (int j = 0; j < kKeysPerThread; ++j) {
-        const bool ok = (wbase + 64 * j + lane) < tend;
+        const bool ok = lane0 + 64u * j < tend;
         const unsigned dd = (key[j] >> shift) & 255u;
         const unsigned p = ok ? loff[dd] + wcnt[wave][dd] + lrank[j] : 0xffffffffu;
         lpos[j] = p < (unsigned)kTile ? p : 0xffffffffu;  // out of range is unreachable for consistent counts
         if (lpos[j] != 0xffffffffu) stage[p] = key[j];
     }
     __syncthreads();
-    const long long valid_ll = tend - tile_base;
-    const int valid = valid_ll < kTile ? (int)valid_ll : kTile;
+    const int valid = (int)(tend - tile_base);  // <= kTile
     unsigned dst[kKeysPerThread];
 #pragma unroll
     for (int k = 0; k < kKeysPerThread; ++k) {
