@@ -809,8 +809,20 @@ __global__ __launch_bounds__(kPartThreads) void k_partition2(const unsigned* __r
     const int tid = threadIdx.x;
     if (tid < kL2) lcnt[tid] = 0u;
     __syncthreads();
-    const unsigned tile = blockIdx.x;  // no waits on other tiles
-    const unsigned b = tile / tiles_per_bucket, k = tile % tiles_per_bucket;
+    // Blocks are dealt to the 8 XCDs round robin; block 8 j + x takes tile j
+    // of XCD x's share, the tiles of buckets x, x + 8, ... in order, so each
+    // bucket's runs (which meet inside cache lines in every sub-bucket) are
+    // written from one L2.  No tile waits on another.
+    const unsigned n_buckets = gridDim.x / tiles_per_bucket;
+    unsigned b, k;
+    if ((n_buckets & 7u) == 0u) {
+        const unsigned x = blockIdx.x & 7u, j = blockIdx.x >> 3;
+        b = x + 8u * (j / tiles_per_bucket);
+        k = j % tiles_per_bucket;
+    } else {
+        b = blockIdx.x / tiles_per_bucket;
+        k = blockIdx.x % tiles_per_bucket;
+    }
     // cell and pair indices fit in 32 bits (n <= 2^30)
     const unsigned bstart = b * S1;
     const unsigned t0 = bstart + k * (unsigned)kPartTile;
