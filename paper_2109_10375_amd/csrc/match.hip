@@ -23,11 +23,8 @@
 
 namespace {
 
-#ifndef AMBER_SCAN_THREADS
-#define AMBER_SCAN_THREADS 256
-#endif
 constexpr int kPer = 16;                            // ranks (or pairs) per thread
-constexpr int kScanThreads = AMBER_SCAN_THREADS;    // tile sums and matching: one tile per block
+constexpr int kScanThreads = 256;                   // tile sums and matching: one tile per block
 constexpr int kScanWaves = kScanThreads / 64;
 constexpr int kScanTile = kScanThreads * kPer;
 constexpr int kPartThreads = 1024;                  // second partition level: 16384 pairs per block

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const float* __restrict__
             const long long i = base + k * kHistThreads + threadIdx.x;
             const bool live = i < n4;
             const unsigned tile = (unsigned)((4 * i) >> tile_shift);
-            unsigned s0 = (unsigned)(((unsigned long long)tile * seg_mul) >> 32);  // < 2^48 before the shift
+            unsigned s0 = (unsigned)(((unsigned long long)tile * seg_mul) >> 32);  // tile < 2^17: no overflow
             s0 = s0 < 8u ? s0 : 7u;
             const float f[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
 #pragma unroll
@@ -663,12 +663,13 @@ int rank_sort(const amber_plan_s* p, const float* d_J, const float* d_w, unsigne
     const long long hist_step = (long long)hist_blocks * kHistThreads * 4;
     if ((long long)kHistWaves * 16 * ((n / 4 + hist_step - 1) / hist_step) > 65535) return AMBER_E_SIZE;
     // pass 0's segments: ranges of tps tiles; tile / tps = (tile * seg_mul) >> 32
-    // exactly for tile < 2^16 (seg_mul <= 2^32)
+    // with seg_mul = ceil(2^32 / tps) = (2^32 + r) / tps, r < tps: exact while
+    // tile * r < 2^32, which n_tiles * tps < 2^32 ensures
     const unsigned tps = (unsigned)((n_tiles + 7) / 8);
     const unsigned long long seg_mul = ((1ULL << 32) + tps - 1) / tps;
     int tile_shift = 0;
     while ((1LL << tile_shift) < tile) ++tile_shift;
-    if (n_tiles > 65536) return AMBER_E_SIZE;
+    if ((unsigned long long)n_tiles * tps >= (1ULL << 32)) return AMBER_E_SIZE;
     // The blocks' segment counts go through the first key buffer (free until
     // pass 1) where it holds them, else straight into the control block.
     constexpr long long kSegWords = 3 * 8 * 256;
