@@ -29,11 +29,8 @@ constexpr int kScanWaves = kScanThreads / 64;
 constexpr int kScanTile = kScanThreads * kPer;
 constexpr int kPartThreads = 1024;                  // second partition level: 16384 pairs per block
 constexpr int kPartTile = kPartThreads * kPer;
-#ifndef AMBER_L1_BUCKETS
-#define AMBER_L1_BUCKETS 128
-#endif
-constexpr int kL1 = AMBER_L1_BUCKETS;  // first-level cell-range buckets
-constexpr int kL2 = 65536 / kL1;       // second-level sub-buckets of each bucket
+constexpr int kL1 = 128;          // first-level cell-range buckets
+constexpr int kL2 = 65536 / kL1;  // second-level sub-buckets of each bucket
 static_assert(kScanThreads >= 256 && kScanTile <= 65536, "tile geometry");
 static_assert(kL1 >= 64 && kL1 % 64 == 0 && kL1 <= kScanThreads && kL2 <= kPartThreads, "bucket geometry");
 constexpr int kMaxHist = 3;
