@@ -23,7 +23,9 @@
 
 namespace {
 
-constexpr int kHistThreads = 256;
+// 1024 threads: the histogram's 56 KB of LDS allow two blocks per CU, which
+// at 256 threads left a streaming read of J with 8 waves per CU.
+constexpr int kHistThreads = 1024;
 constexpr int kHistWaves = kHistThreads / 64;
 constexpr int kKeysPerThread = 16;
 // One onesweep tile per block: 16384 keys (1024 threads) on large grids, where
