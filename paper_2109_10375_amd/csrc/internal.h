@@ -98,7 +98,6 @@ struct Ctrl {
     unsigned status;            // AMBER_STATUS_* bits of this call
     unsigned pad0;
     unsigned* sticky;           // the plan's accumulated status word (amber_status clears it)
-    unsigned tickets[32];       // tile tickets: 0-3 radix passes, 4.. matching launches
     unsigned hist[4][256];      // digit histograms of the descending keys
     unsigned digit_off[4][256]; // exclusive prefix of hist
     unsigned long long msum[256];  // per-FP32-exponent sums of significands of w

@@ -9,14 +9,16 @@
 // and every pass is stable, so equal intensities keep ascending cell index.
 //
 // Each pass ("onesweep"): a block takes the next tile (16384 keys on large
-// grids, 4096 on small ones) from a ticket counter, ranks its keys by digit
-// within each wave (the lanes that share a digit find each other through a
-// per-digit LDS mask, or in the last pass with 8 ballots; the lowest of them
-// bumps the wave's LDS counter), publishes its per-digit counts for later tiles and looks back over
-// earlier tiles' published counts (decoupled look-back) to find where its
-// digits start globally, then writes its keys digit by digit through LDS so
-// that each digit's run is stored contiguously.  Tiles only wait on tiles that
-// took earlier tickets, which are already running, so every wait ends.
+// grids, 4096 on small ones) of one of the pass's input segments from that
+// segment's ticket counter, ranks its keys by digit within each wave (the
+// lanes that share a digit find each other through a per-digit LDS mask, or
+// in the last pass with 8 ballots; the lowest of them bumps the wave's LDS
+// counter), publishes its per-digit counts for the segment's later tiles and
+// looks back over the segment's earlier tiles' published counts (decoupled
+// look-back) to find where its digits start, then writes its keys digit by
+// digit through LDS so that each digit's run is stored contiguously.  Tiles
+// only wait on tiles that took earlier tickets, which are already running, so
+// every wait ends.
 #include <algorithm>
 
 #include "internal.h"
