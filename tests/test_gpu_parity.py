@@ -74,6 +74,45 @@ def test_rank_adversarial(amber, kind):
     assert np.array_equal(perm.cpu().numpy().view(np.uint32), oracle.rank(J))
 
 
+def _few_bits_intensity(n, seed):
+    """Intensities with at most 8 significant bits: the two low bytes of every
+    sort key take one value, so the radix passes that split their input by
+    those bytes' top bits find every key in one of their 8 segments."""
+    rng = np.random.default_rng(seed)
+    J = (rng.integers(1, 256, n ** 3) * np.exp2(rng.integers(-12, 12, n ** 3))).astype(np.float32)
+    assert not np.any(J.view(np.uint32) & 0xFFFF)
+    return J
+
+
+def test_rank_one_segment_takes_all_tiles(amber):
+    """All 4096 tiles of the second and third radix passes at 256^3 in one
+    input segment: every block takes its tile from that segment after finding
+    its own empty.  The permutation is still the oracle's, bit for bit."""
+    n = 256
+    print("rank one segment n=256", flush=True)
+    J = _few_bits_intensity(n, 41)
+    plan = amber.Plan(n, 1.0)
+    perm = plan.rank(torch.from_numpy(J).cuda())
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    assert np.array_equal(perm.cpu().numpy().view(np.uint32), oracle.rank(J))
+
+
+def test_zre_one_segment_takes_all_tiles(amber):
+    """The same concentration on the weighted ranking that matching uses."""
+    n = 128
+    print("zre one segment n=128", flush=True)
+    J = torch.from_numpy(_few_bits_intensity(n, 43).reshape(n, n, n))
+    w = inputs.make_density(n, 44).to(torch.float32)
+    H = _oracle_hist((8.0, 4.0, 3.0))
+    plan = amber.Plan(n, 1.0)
+    (z,) = plan.zre(J.cuda(), w.cuda(), [_gpu_hist(amber, H)])
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    z_ref, _ = oracle.zre(J.numpy(), w.numpy(), H, mode=oracle.CONTRACT)
+    assert np.array_equal(z.cpu().numpy(), z_ref)
+
+
 def test_rank_nan_sets_status(amber):
     n = 16
     J = inputs.make_intensity(n, 3)
