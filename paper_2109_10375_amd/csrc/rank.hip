@@ -308,9 +308,10 @@ __device__ __forceinline__ void last_pass_stores(const unsigned* key, const unsi
 // weights) are written.  CARRY: weights travel with the keys; pass 0 also
 // checks them and stores the smallest ulp exponent of each tile in qtile[tile].
 //
-// The input is split into 8 segments, each cut into tiles from its start with
-// a ticket counter and a look-back chain of its own; the runs a segment's keys
-// form start at offsets the histogram kernel counted.  A block takes a tile of
+// The input of passes 0-2 is split into 8 segments (the last pass's is one),
+// each cut into tiles from its start with a ticket counter and a look-back
+// chain of its own; the runs a segment's keys form start at offsets the
+// histogram kernel counted.  A block takes a tile of
 // segment blockIdx % 8 and of the next segments once that one is used up, so
 // consecutive tiles, whose digit runs meet inside cache lines, are written
 // from the same XCD's L2 (blocks are dealt to the 8 XCDs round robin) while
